@@ -1,0 +1,192 @@
+/*
+ * tina_pfb.h -- C ABI of the MI355X (gfx950) polyphase filter bank channelizer.
+ *
+ * The filter bank follows the TINA paper (arXiv 2408.16551), Sec. 5.2,
+ * Eq. (20): an input stream x(n) is split into P branches x_p(n'), each branch
+ * is filtered by its share h_p of the prototype filter taps,
+ *     y_p(n') = sum_{m=0}^{M-1} h_p(m) x_p(n'-m),
+ * and each frame of branch outputs goes through a DFT across the P branches
+ * (Sec. 4.1, Eq. (12): Z = X F, F the Fourier matrix).  Readings used where
+ * the paper is silent:
+ *   - branch p of frame f is sample f*P + p of the stream;
+ *   - h_p(m) = h[(M-1-m)*P + p] for a prototype h of length L = P*M;
+ *   - the DFT is forward and unnormalised, X[k] = sum_p y[p] exp(-2 pi i p k/P);
+ *   - a real stream yields channels k = 0..P/2, a complex stream k = 0..P-1.
+ *
+ * Conventions for every call:
+ *   - The return value is a tina_status; TINA_OK is 0.  On failure a message
+ *     is available from tina_last_error() (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this boundary.
+ *   - Arguments are validated before any work is enqueued, so a call that
+ *     fails validation has not written to any output.
+ *   - "Device pointer" means memory the caller allocated on the plan's HIP
+ *     device (hipMalloc, or a torch tensor's data_ptr()).  The library never
+ *     frees caller memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Device work is asynchronous on that stream unless stated otherwise.
+ *   - Sizes are int64_t counts of samples or frames, never bytes, unless the
+ *     name says _bytes.
+ */
+#ifndef TINA_PFB_H
+#define TINA_PFB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tina_status {
+    TINA_OK = 0,
+    TINA_ERR_INVALID_ARGUMENT = 1, /* a NULL handle/pointer, a bad size or alignment */
+    TINA_ERR_UNSUPPORTED = 2,      /* valid request this build does not implement */
+    TINA_ERR_OUT_OF_MEMORY = 3,    /* a device or host allocation failed */
+    TINA_ERR_DEVICE = 4,           /* a HIP runtime call failed */
+    TINA_ERR_BUSY = 5,             /* a queue is full; retry later */
+    TINA_ERR_NOT_READY = 6,        /* the result is not complete yet */
+    TINA_ERR_TOO_LARGE = 7,        /* the request can never fit the configured budget */
+    TINA_ERR_TIMEOUT = 8,          /* a wait ran out of time */
+    TINA_ERR_CANCELLED = 9         /* the request was cancelled or its server stopped */
+} tina_status;
+
+typedef enum tina_sample_type {
+    TINA_SAMPLE_R32 = 0, /* real float32 samples */
+    TINA_SAMPLE_C64 = 1  /* complex64 samples: interleaved float32 re, im */
+} tina_sample_type;
+
+/* Prototype window.  The prototype is h[n] = sinc((n - (L-1)/2) / P) * w[n],
+ * n = 0..L-1, L = P*M, sinc(t) = sin(pi t)/(pi t), with a symmetric window w
+ * over L points: rect 1; Hann 0.5 - 0.5 cos(2 pi n/(L-1));
+ * Hamming 0.54 - 0.46 cos(2 pi n/(L-1));
+ * Blackman 0.42 - 0.5 cos(2 pi n/(L-1)) + 0.08 cos(4 pi n/(L-1)).
+ * No normalisation.  CUSTOM takes h from the descriptor instead. */
+typedef enum tina_window {
+    TINA_WINDOW_RECT = 0,
+    TINA_WINDOW_HANN = 1,
+    TINA_WINDOW_HAMMING = 2,
+    TINA_WINDOW_BLACKMAN = 3,
+    TINA_WINDOW_CUSTOM = 4
+} tina_window;
+
+/* Arithmetic of the DFT stage (a matrix product on the MFMA units, FP32
+ * accumulation).  The FIR stage is always FP32.
+ *   FP32       plain FP32 operands.
+ *   BF16       operands rounded to bfloat16.
+ *   BF16X3     operands split into bfloat16 hi + lo pieces, three products
+ *              (hi*hi + hi*lo + lo*hi).
+ *   FP16       operands rounded to float16, each frame scaled by a power of
+ *              two so that its largest branch output fits the format.
+ *   FP16X3     float16 hi + lo pieces (lo scaled by 2^11), three products,
+ *              same per-frame power-of-two scale.
+ *   FP8_FRAME  operands in FP8 E4M3 (OCP), each frame scaled by a power of two
+ *              so that its largest branch output maps to at most 448. */
+typedef enum tina_precision {
+    TINA_PREC_FP32 = 0,
+    TINA_PREC_BF16 = 1,
+    TINA_PREC_BF16X3 = 2,
+    TINA_PREC_FP16 = 3,
+    TINA_PREC_FP16X3 = 4,
+    TINA_PREC_FP8_FRAME = 5
+} tina_precision;
+
+typedef enum tina_output {
+    TINA_OUT_PFB = 0,     /* channelizer output: frames x K complex64 */
+    TINA_OUT_FIR_ONLY = 1 /* polyphase FIR output only: frames x P samples of the input type */
+} tina_output;
+
+typedef struct tina_pfb_desc {
+    uint32_t struct_size;      /* sizeof(tina_pfb_desc) */
+    int32_t channels;          /* P: power of two, 16 <= P <= 8192 */
+    int32_t taps;              /* M: taps per branch, 1 <= M <= 64 */
+    int32_t sample_type;       /* tina_sample_type */
+    int32_t window;            /* tina_window */
+    int32_t precision;         /* tina_precision (ignored for TINA_OUT_FIR_ONLY) */
+    int32_t output;            /* tina_output */
+    int32_t device;            /* HIP device ordinal */
+    const double* custom_taps; /* host, P*M doubles, read during tina_pfb_plan when
+                                  window == TINA_WINDOW_CUSTOM; otherwise NULL */
+} tina_pfb_desc;
+
+typedef struct tina_pfb_plan_s* tina_pfb_plan_t;
+typedef struct tina_pfb_state_s* tina_pfb_state_t;
+
+/* Last error message of the calling thread ("" if none). */
+const char* tina_last_error(void);
+
+/* Library version string. */
+const char* tina_version(void);
+
+/*
+ * Create a plan: designs the prototype window and the DFT operand (the
+ * Fourier matrix of Sec. 4.1 in the operand form of the chosen precision) on
+ * the device in FP64, then rounds them to the forms the kernels use.  The
+ * plan owns all of its device memory, including a workspace sized for
+ * `max_chunk_frames`-frame pieces (execute splits larger inputs), and
+ * synchronises once before returning.
+ * Errors: INVALID_ARGUMENT (bad descriptor), UNSUPPORTED (P or M outside the
+ * ranges above), OUT_OF_MEMORY, DEVICE.
+ */
+tina_status tina_pfb_plan(const tina_pfb_desc* desc, tina_pfb_plan_t* out_plan);
+
+/* Release a plan and its device memory (synchronises its device first).
+ * NULL is accepted. */
+tina_status tina_pfb_plan_destroy(tina_pfb_plan_t plan);
+
+/* Number of output channels per frame: P/2+1 (real input) or P (complex), or
+ * P for TINA_OUT_FIR_ONLY. */
+tina_status tina_pfb_channels_out(tina_pfb_plan_t plan, int64_t* channels);
+
+/* Copy the plan's FP64 prototype taps h[0..P*M) to host memory (P*M
+ * doubles).  Synchronous. */
+tina_status tina_pfb_plan_taps(tina_pfb_plan_t plan, double* host_taps);
+
+/* Frames that tina_pfb_execute will produce for n_samples new samples:
+ * floor((r + n_samples)/P) where r is the state's residue (0 without state). */
+tina_status tina_pfb_output_frames(tina_pfb_plan_t plan, tina_pfb_state_t state,
+                                   int64_t n_samples, int64_t* frames);
+
+/*
+ * Run the filter bank on n_samples samples at d_in (device pointer; float32
+ * or complex64 per the plan; 4-byte aligned for R32, 8-byte for C64).
+ *
+ * Without a state (state == NULL) the history before the first sample is
+ * zero, frames = floor(n_samples / P), trailing samples that do not fill a
+ * frame are ignored, and nothing is retained.  With a state, the stream's
+ * last (M-1)*P samples and its partial-frame residue are prepended, the
+ * frames completed by this chunk are produced, and the state is updated on
+ * `stream` after them (the state must not be used concurrently on another
+ * stream).
+ *
+ * Output at d_out (device pointer, 8-byte aligned), row-major:
+ *   TINA_OUT_PFB:      frames x channels_out complex64 (interleaved float32);
+ *   TINA_OUT_FIR_ONLY: frames x P samples of the input type.
+ * out_capacity_frames is the number of frames d_out can hold; it must be at
+ * least the frame count, else INVALID_ARGUMENT and nothing is enqueued.
+ * *frames_written (may be NULL) receives the frame count.
+ * The call enqueues work on `stream` and returns without synchronising; the
+ * caller keeps d_in and d_out alive until that work is complete.
+ */
+tina_status tina_pfb_execute(tina_pfb_plan_t plan, const void* d_in, int64_t n_samples,
+                             void* d_out, int64_t out_capacity_frames,
+                             tina_pfb_state_t state, int64_t* frames_written, void* stream);
+
+/* Per-stream filter state: (M-1)*P history samples plus fewer than P
+ * residue samples, in device memory owned by the state.  Created zeroed. */
+tina_status tina_pfb_state_create(tina_pfb_plan_t plan, tina_pfb_state_t* out_state);
+tina_status tina_pfb_state_destroy(tina_pfb_state_t state);
+/* Zero the history and drop the residue (synchronous). */
+tina_status tina_pfb_state_reset(tina_pfb_state_t state);
+/* Samples held: (M-1)*P + residue.  Sample size is 4 (R32) or 8 (C64) bytes. */
+tina_status tina_pfb_state_size(tina_pfb_state_t state, int64_t* n_samples, int64_t* residue);
+/* Copy the state to host memory: (M-1)*P history samples followed by the
+ * residue, capacity in samples.  Synchronous. */
+tina_status tina_pfb_state_export(tina_pfb_state_t state, void* host_buf, int64_t capacity,
+                                  int64_t* n_samples);
+/* Load a state exported by a plan with the same P, M and sample type:
+ * n_samples = (M-1)*P + residue with 0 <= residue < P.  Synchronous. */
+tina_status tina_pfb_state_import(tina_pfb_state_t state, const void* host_buf, int64_t n_samples);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TINA_PFB_H */

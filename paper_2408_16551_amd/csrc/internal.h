@@ -1,0 +1,78 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tina {
+
+// Arithmetic forms of the DFT stage (same values as tina_precision).
+enum Form : int { FORM_FP32 = 0, FORM_BF16 = 1, FORM_BF16X3 = 2, FORM_FP16 = 3, FORM_FP16X3 = 4, FORM_FP8 = 5 };
+
+inline bool form_scaled(int f) { return f == FORM_FP16 || f == FORM_FP16X3 || f == FORM_FP8; }
+inline int form_pieces(int f) { return (f == FORM_BF16X3 || f == FORM_FP16X3) ? 2 : 1; }
+inline int form_elem_bytes(int f) { return f == FORM_FP32 ? 4 : (f == FORM_FP8 ? 1 : 2); }
+
+// Map a hardware block index to a logical tile index so that the blocks the
+// dispatcher places on one XCD (it deals blocks round-robin over the 8 XCDs)
+// receive consecutive logical tiles, which then share that XCD's L2.
+__device__ inline int64_t xcd_logical_block(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, i = b >> 3;
+    const int64_t q = nb >> 3, rmd = nb & 7;
+    return x * q + (x < rmd ? x : rmd) + i;
+}
+
+// ---------------------------------------------------------------- generation
+// Prototype window h[n], n < P*M, in FP64 (sinc x window), plus its FP32 copy.
+hipError_t launch_window(double* h64, float* h32, int P, int M, int window, hipStream_t s);
+// FP32 copy of FP64 taps (custom window).
+hipError_t launch_taps_to_f32(const double* h64, float* h32, int64_t L, hipStream_t s);
+// DFT operand Bt[N][K] (row n = output column, K contiguous) in the pieces of
+// `form`: piece0 (and piece1 for split forms), element size form_elem_bytes.
+hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int complex_input, int form,
+                              hipStream_t s);
+
+// ----------------------------------------------------------------------- FIR
+struct FirArgs {
+    const float* prefix;  // history + residue (floats); nullptr = zeros
+    int64_t plen;         // floats in the prefix
+    const float* chunk;   // new samples (floats)
+    int64_t nchunk;       // floats in the chunk
+    const float* taps;    // FP32 prototype h[0..P*M)
+    float* y;             // output rows
+    int64_t ldy;          // floats per output row
+    int64_t g0;           // first output frame (frame numbering of prefix-residue ++ chunk)
+    int64_t F;            // frames to produce
+    int32_t W;            // floats per frame (P * cf)
+    int32_t P, M, cf;     // channels, taps, floats per sample
+    float* amax;          // optional per-frame partial |y| maxima [F][nparts]
+    int32_t nparts;       // filled in by launch_fir
+};
+// Chooses the vector width and unroll; returns the number of partial maxima
+// per frame through a.nparts when a.amax is set.
+hipError_t launch_fir(FirArgs& a, hipStream_t s);
+// Number of partial maxima per frame launch_fir would produce.
+int fir_amax_parts(const FirArgs& a);
+
+// dst[i] = ext[start + i], i < count, where ext = prefix ++ chunk (floats).
+hipError_t launch_gather_ext(const float* prefix, int64_t plen, const float* chunk, int64_t nchunk,
+                             float* dst, int64_t start, int64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------------- GEMM
+struct GemmArgs {
+    const float* A;        // FIR output [F][K] FP32, row stride lda
+    int64_t lda;
+    const void* B0;        // Bt piece 0 [N][K]
+    const void* B1;        // Bt piece 1 (split forms)
+    const float* amax;     // per-frame partial maxima [F][nparts] (scaled forms)
+    int32_t nparts;
+    float* out;            // output rows (floats), row stride ldo
+    int64_t ldo;
+    int64_t F;
+    int32_t K, N;
+    int32_t real_pack;     // real input: column 0 -> X_0, column 1 -> X_{P/2}, rest in place
+    int32_t form;
+};
+hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
+
+}  // namespace tina

@@ -1,0 +1,354 @@
+// C ABI: plans, per-stream state and the execute call of the filter bank.
+//
+// Execute enqueues, on the caller's stream:
+//   1. the polyphase FIR (fir.hip) over history ++ residue ++ new samples,
+//      into the caller's output (FIR-only plans) or into the plan's FP32
+//      workspace, with per-frame |y| maxima for the scaled forms;
+//   2. the DFT-across-branches GEMM (gemm.hip) from the workspace into the
+//      caller's complex64 output;
+//   3. with a state: the new history and residue gathered into the state's
+//      other buffer (ping-pong, so the FIR of this call still reads the old one).
+// Inputs larger than the workspace run as consecutive frame pieces.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "tina_pfb.h"
+
+using namespace tina;
+
+namespace {
+
+thread_local std::string g_err;
+
+tina_status fail(tina_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail(TINA_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Makes `dev` current for the scope of a call and restores the caller's device.
+struct DeviceScope {
+    int prev = -1, dev;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int d) : dev(d) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr int64_t kWorkspaceBytes = 512ll << 20;  // FP32 FIR output per piece
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+struct tina_pfb_plan_s {
+    int device = 0;
+    int P = 0, M = 0, cf = 1, W = 0;  // W = floats per frame
+    int K = 0, N = 0;                 // GEMM inner and column dims
+    int64_t kout = 0;                 // output channels (or P for FIR-only)
+    int sample_type = 0, window = 0, precision = 0, output = 0;
+    double* h64 = nullptr;
+    float* h32 = nullptr;
+    void* B[2] = {nullptr, nullptr};
+    float* ws = nullptr;
+    float* amax = nullptr;
+    int64_t ch_frames = 0;
+    int64_t amax_parts_cap = 0;
+
+    void release() {
+        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax})
+            if (p) (void)hipFree(p);
+        h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr;
+    }
+};
+
+struct tina_pfb_state_s {
+    tina_pfb_plan_s* plan = nullptr;
+    float* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t residue = 0;     // samples
+    int64_t cap_floats = 0;  // floats per buffer
+};
+
+extern "C" {
+
+const char* tina_last_error(void) { return g_err.c_str(); }
+
+const char* tina_version(void) { return "tina_pfb 0.1 (gfx950)"; }
+
+tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
+    if (!d || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: NULL descriptor or output handle");
+    *out = nullptr;
+    if (d->struct_size < sizeof(tina_pfb_desc)) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
+    if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
+    if (d->window < TINA_WINDOW_RECT || d->window > TINA_WINDOW_CUSTOM)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown window");
+    if (d->output != TINA_OUT_PFB && d->output != TINA_OUT_FIR_ONLY)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown output");
+    if (d->output == TINA_OUT_PFB && (d->precision < TINA_PREC_FP32 || d->precision > TINA_PREC_FP8_FRAME))
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown precision");
+    if (d->window == TINA_WINDOW_CUSTOM && !d->custom_taps)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: CUSTOM window without custom_taps");
+    if (d->channels <= 0 || d->taps <= 0) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: channels and taps must be positive");
+    if (!is_pow2(d->channels) || d->channels < 16 || d->channels > 8192)
+        return fail(TINA_ERR_UNSUPPORTED, "plan: channels must be a power of two in [16, 8192]");
+    if (d->taps > 64) return fail(TINA_ERR_UNSUPPORTED, "plan: taps must be in [1, 64]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TINA_ERR_DEVICE, "plan: no HIP device");
+    if (d->device < 0 || d->device >= ndev) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: bad device ordinal");
+
+    DeviceScope ds(d->device);
+    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "plan: hipSetDevice failed");
+
+    tina_pfb_plan_s* p = new (std::nothrow) tina_pfb_plan_s();
+    if (!p) return fail(TINA_ERR_OUT_OF_MEMORY, "plan: host allocation");
+    p->device = d->device;
+    p->P = d->channels;
+    p->M = d->taps;
+    p->sample_type = d->sample_type;
+    p->cf = d->sample_type == TINA_SAMPLE_C64 ? 2 : 1;
+    p->W = p->P * p->cf;
+    p->window = d->window;
+    p->precision = d->output == TINA_OUT_PFB ? d->precision : TINA_PREC_FP32;
+    p->output = d->output;
+    p->K = p->W;
+    p->N = p->W;
+    p->kout = d->output == TINA_OUT_FIR_ONLY ? p->P : (p->cf == 2 ? p->P : p->P / 2 + 1);
+
+    auto bail = [&](tina_status st, const std::string& m) {
+        p->release();
+        delete p;
+        return fail(st, m);
+    };
+    const int64_t L = (int64_t)p->P * p->M;
+    if (hipMalloc(&p->h64, L * sizeof(double)) != hipSuccess || hipMalloc(&p->h32, L * sizeof(float)) != hipSuccess)
+        return bail(TINA_ERR_OUT_OF_MEMORY, "plan: taps allocation");
+    hipError_t e;
+    if (d->window == TINA_WINDOW_CUSTOM) {
+        e = hipMemcpy(p->h64, d->custom_taps, L * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_taps_to_f32(p->h64, p->h32, L, nullptr);
+    } else {
+        e = launch_window(p->h64, p->h32, p->P, p->M, d->window, nullptr);
+    }
+    if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: taps: ") + hipGetErrorString(e));
+
+    if (p->output == TINA_OUT_PFB) {
+        const int form = p->precision;
+        const int64_t nbytes = (int64_t)p->N * p->K * form_elem_bytes(form);
+        for (int i = 0; i < form_pieces(form); ++i)
+            if (hipMalloc(&p->B[i], nbytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: DFT operand allocation");
+        e = launch_dft_operand(p->B[0], p->B[1], p->P, p->cf == 2, form, nullptr);
+        if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: DFT operand: ") + hipGetErrorString(e));
+        p->ch_frames = kWorkspaceBytes / ((int64_t)p->W * 4);
+        p->ch_frames = p->ch_frames >= 128 ? (p->ch_frames / 128) * 128 : p->ch_frames;
+        if (p->ch_frames < 1) p->ch_frames = 1;
+        if (hipMalloc(&p->ws, p->ch_frames * p->W * sizeof(float)) != hipSuccess)
+            return bail(TINA_ERR_OUT_OF_MEMORY, "plan: workspace allocation");
+        if (form_scaled(form)) {
+            p->amax_parts_cap = p->W / 64 > 1 ? p->W / 64 : 1;
+            if (hipMalloc(&p->amax, p->ch_frames * p->amax_parts_cap * sizeof(float)) != hipSuccess)
+                return bail(TINA_ERR_OUT_OF_MEMORY, "plan: scale workspace allocation");
+        }
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: ") + hipGetErrorString(e));
+    *out = p;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_plan_destroy(tina_pfb_plan_t p) {
+    if (!p) return TINA_OK;
+    DeviceScope ds(p->device);
+    (void)hipDeviceSynchronize();
+    p->release();
+    delete p;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_channels_out(tina_pfb_plan_t p, int64_t* ch) {
+    if (!p || !ch) return fail(TINA_ERR_INVALID_ARGUMENT, "channels_out: NULL argument");
+    *ch = p->kout;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_plan_taps(tina_pfb_plan_t p, double* host) {
+    if (!p || !host) return fail(TINA_ERR_INVALID_ARGUMENT, "plan_taps: NULL argument");
+    DeviceScope ds(p->device);
+    HIP_TRY(hipMemcpy(host, p->h64, (size_t)p->P * p->M * sizeof(double), hipMemcpyDeviceToHost));
+    return TINA_OK;
+}
+
+tina_status tina_pfb_output_frames(tina_pfb_plan_t p, tina_pfb_state_t st, int64_t n, int64_t* frames) {
+    if (!p || !frames) return fail(TINA_ERR_INVALID_ARGUMENT, "output_frames: NULL argument");
+    if (n < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "output_frames: negative sample count");
+    if (st && st->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, "output_frames: state belongs to another plan");
+    const int64_t r = st ? st->residue : 0;
+    *frames = (r + n) / p->P;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, void* d_out, int64_t cap,
+                             tina_pfb_state_t st, int64_t* frames_written, void* stream) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL plan");
+    if (n < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: negative sample count");
+    if (n > 0 && !d_in) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL input");
+    if (st && st->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: state belongs to another plan");
+    const size_t sbytes = p->cf * sizeof(float);
+    if ((uintptr_t)d_in % sbytes) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: input not aligned to its sample size");
+    const int64_t r = st ? st->residue : 0;
+    const int64_t F = (r + n) / p->P;
+    if (F > 0 && !d_out) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL output");
+    const size_t obytes = p->output == TINA_OUT_PFB ? 8 : sbytes;
+    if ((uintptr_t)d_out % obytes) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output misaligned");
+    if (F > cap) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output capacity (" + std::to_string(cap) +
+                                                         " frames) below frame count " + std::to_string(F));
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute: hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+
+    FirArgs fa{};
+    fa.prefix = st ? st->buf[st->cur] : nullptr;
+    fa.plen = (int64_t)(p->M - 1) * p->W + r * p->cf;
+    fa.chunk = (const float*)d_in;
+    fa.nchunk = n * p->cf;
+    fa.taps = p->h32;
+    fa.W = p->W;
+    fa.P = p->P;
+    fa.M = p->M;
+    fa.cf = p->cf;
+
+    if (p->output == TINA_OUT_FIR_ONLY) {
+        fa.y = (float*)d_out;
+        fa.ldy = p->W;
+        fa.g0 = 0;
+        fa.F = F;
+        fa.amax = nullptr;
+        HIP_TRY(launch_fir(fa, s));
+    } else {
+        const int form = p->precision;
+        const int64_t ldo = p->cf == 2 ? 2 * (int64_t)p->P : (int64_t)p->P + 2;
+        for (int64_t c0 = 0; c0 < F; c0 += p->ch_frames) {
+            const int64_t Fc = F - c0 < p->ch_frames ? F - c0 : p->ch_frames;
+            fa.y = p->ws;
+            fa.ldy = p->W;
+            fa.g0 = c0;
+            fa.F = Fc;
+            fa.amax = form_scaled(form) ? p->amax : nullptr;
+            HIP_TRY(launch_fir(fa, s));
+            GemmArgs ga{};
+            ga.A = p->ws;
+            ga.lda = p->W;
+            ga.B0 = p->B[0];
+            ga.B1 = p->B[1];
+            ga.amax = fa.amax;
+            ga.nparts = fa.nparts;
+            ga.out = (float*)d_out + c0 * ldo;
+            ga.ldo = ldo;
+            ga.F = Fc;
+            ga.K = p->K;
+            ga.N = p->N;
+            ga.real_pack = p->cf == 1;
+            ga.form = form;
+            HIP_TRY(launch_dft_gemm(ga, s));
+        }
+    }
+    if (st) {
+        const int64_t r2 = (r + n) % p->P;
+        const int64_t count = (int64_t)(p->M - 1) * p->W + r2 * p->cf;
+        HIP_TRY(launch_gather_ext(fa.prefix, fa.plen, fa.chunk, fa.nchunk, st->buf[st->cur ^ 1], F * p->W, count, s));
+        st->cur ^= 1;
+        st->residue = r2;
+    }
+    if (frames_written) *frames_written = F;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_create(tina_pfb_plan_t p, tina_pfb_state_t* out) {
+    if (!p || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "state_create: NULL argument");
+    *out = nullptr;
+    DeviceScope ds(p->device);
+    tina_pfb_state_s* st = new (std::nothrow) tina_pfb_state_s();
+    if (!st) return fail(TINA_ERR_OUT_OF_MEMORY, "state_create: host allocation");
+    st->plan = p;
+    st->cap_floats = (int64_t)p->M * p->W;  // (M-1)*W history + up to W residue floats
+    for (int i = 0; i < 2; ++i) {
+        if (hipMalloc(&st->buf[i], st->cap_floats * sizeof(float)) != hipSuccess ||
+            hipMemset(st->buf[i], 0, st->cap_floats * sizeof(float)) != hipSuccess) {
+            for (float* b : st->buf)
+                if (b) (void)hipFree(b);
+            delete st;
+            return fail(TINA_ERR_OUT_OF_MEMORY, "state_create: device allocation");
+        }
+    }
+    *out = st;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_destroy(tina_pfb_state_t st) {
+    if (!st) return TINA_OK;
+    DeviceScope ds(st->plan->device);
+    (void)hipDeviceSynchronize();
+    for (float* b : st->buf)
+        if (b) (void)hipFree(b);
+    delete st;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_reset(tina_pfb_state_t st) {
+    if (!st) return fail(TINA_ERR_INVALID_ARGUMENT, "state_reset: NULL state");
+    DeviceScope ds(st->plan->device);
+    HIP_TRY(hipDeviceSynchronize());
+    for (float* b : st->buf) HIP_TRY(hipMemset(b, 0, st->cap_floats * sizeof(float)));
+    st->cur = 0;
+    st->residue = 0;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_size(tina_pfb_state_t st, int64_t* n, int64_t* residue) {
+    if (!st) return fail(TINA_ERR_INVALID_ARGUMENT, "state_size: NULL state");
+    const tina_pfb_plan_s* p = st->plan;
+    if (n) *n = (int64_t)(p->M - 1) * p->P + st->residue;
+    if (residue) *residue = st->residue;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_export(tina_pfb_state_t st, void* host, int64_t capacity, int64_t* n_samples) {
+    if (!st || !host) return fail(TINA_ERR_INVALID_ARGUMENT, "state_export: NULL argument");
+    const tina_pfb_plan_s* p = st->plan;
+    const int64_t n = (int64_t)(p->M - 1) * p->P + st->residue;
+    if (capacity < n) return fail(TINA_ERR_INVALID_ARGUMENT, "state_export: host buffer too small");
+    DeviceScope ds(p->device);
+    HIP_TRY(hipDeviceSynchronize());
+    if (n > 0) HIP_TRY(hipMemcpy(host, st->buf[st->cur], n * p->cf * sizeof(float), hipMemcpyDeviceToHost));
+    if (n_samples) *n_samples = n;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_state_import(tina_pfb_state_t st, const void* host, int64_t n) {
+    if (!st || (!host && n > 0)) return fail(TINA_ERR_INVALID_ARGUMENT, "state_import: NULL argument");
+    const tina_pfb_plan_s* p = st->plan;
+    const int64_t hist = (int64_t)(p->M - 1) * p->P;
+    if (n < hist || n - hist >= p->P) return fail(TINA_ERR_INVALID_ARGUMENT, "state_import: sample count must be (M-1)*P + residue, residue < P");
+    DeviceScope ds(p->device);
+    HIP_TRY(hipDeviceSynchronize());
+    if (n > 0) HIP_TRY(hipMemcpy(st->buf[0], host, n * p->cf * sizeof(float), hipMemcpyHostToDevice));
+    st->cur = 0;
+    st->residue = n - hist;
+    return TINA_OK;
+}
+
+}  // extern "C"

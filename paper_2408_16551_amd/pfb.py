@@ -1,0 +1,216 @@
+"""ctypes binding of the C ABI in include/tina_pfb.h.
+
+Argument marshalling only: every step of the filter bank runs in the HIP
+library.  torch supplies device memory (tensor data pointers) and streams.
+If libtina_pfb.so is missing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtina_pfb.so")
+
+SAMPLE = {"r32": 0, "c64": 1}
+WINDOW = {"rect": 0, "hann": 1, "hamming": 2, "blackman": 3, "custom": 4}
+PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5}
+OUTPUT = {"pfb": 0, "fir": 1}
+
+STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
+          5: "BUSY", 6: "NOT_READY", 7: "TOO_LARGE", 8: "TIMEOUT", 9: "CANCELLED"}
+
+# Every symbol include/tina_pfb.h (and the other public headers) declare.
+EXPORTS = [
+    "tina_last_error", "tina_version",
+    "tina_pfb_plan", "tina_pfb_plan_destroy", "tina_pfb_channels_out", "tina_pfb_plan_taps",
+    "tina_pfb_output_frames", "tina_pfb_execute",
+    "tina_pfb_state_create", "tina_pfb_state_destroy", "tina_pfb_state_reset", "tina_pfb_state_size",
+    "tina_pfb_state_export", "tina_pfb_state_import",
+]
+
+
+class TinaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("channels", ctypes.c_int32), ("taps", ctypes.c_int32),
+                ("sample_type", ctypes.c_int32), ("window", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("output", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("custom_taps", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "tina_last_error": ([], ctypes.c_char_p),
+        "tina_version": ([], ctypes.c_char_p),
+        "tina_pfb_plan": ([ctypes.POINTER(_Desc), ctypes.POINTER(vp)], i32),
+        "tina_pfb_plan_destroy": ([vp], i32),
+        "tina_pfb_channels_out": ([vp, P64], i32),
+        "tina_pfb_plan_taps": ([vp, vp], i32),
+        "tina_pfb_output_frames": ([vp, vp, i64, P64], i32),
+        "tina_pfb_execute": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
+        "tina_pfb_state_create": ([vp, ctypes.POINTER(vp)], i32),
+        "tina_pfb_state_destroy": ([vp], i32),
+        "tina_pfb_state_reset": ([vp], i32),
+        "tina_pfb_state_size": ([vp, P64, P64], i32),
+        "tina_pfb_state_export": ([vp, vp, i64, P64], i32),
+        "tina_pfb_state_import": ([vp, vp, i64], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes, fn.restype = args, res
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != 0:
+        raise TinaError(status, load().tina_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A filter-bank plan: P channels, M taps per branch, a prototype window,
+    the sample type, the DFT precision form and the output kind."""
+
+    def __init__(self, channels: int, taps: int, sample_type: str = "r32", window: str = "hann",
+                 precision: str = "fp32", output: str = "pfb", device: int = 0, custom_taps=None):
+        lib = load()
+        self.P, self.M = int(channels), int(taps)
+        self.sample_type, self.precision, self.output = sample_type, precision, output
+        self.complex_input = sample_type == "c64"
+        d = _Desc()
+        d.struct_size = ctypes.sizeof(_Desc)
+        d.channels, d.taps = self.P, self.M
+        d.sample_type, d.window = SAMPLE[sample_type], WINDOW[window]
+        d.precision, d.output, d.device = PRECISION[precision], OUTPUT[output], int(device)
+        self._custom = None
+        if custom_taps is not None:
+            self._custom = np.ascontiguousarray(custom_taps, dtype=np.float64)
+            d.custom_taps = self._custom.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        check(lib.tina_pfb_plan(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        check(lib.tina_pfb_channels_out(self.handle, ctypes.byref(n)))
+        self.channels_out = n.value
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tina_pfb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def taps(self) -> np.ndarray:
+        h = np.empty(self.P * self.M, dtype=np.float64)
+        check(load().tina_pfb_plan_taps(self.handle, h.ctypes.data_as(ctypes.c_void_p)))
+        return h
+
+    def output_frames(self, n_samples: int, state: "State | None" = None) -> int:
+        f = ctypes.c_int64()
+        check(load().tina_pfb_output_frames(self.handle, state.handle if state else None, int(n_samples),
+                                            ctypes.byref(f)))
+        return f.value
+
+    def out_shape(self, frames: int):
+        return (frames, self.channels_out)
+
+    def alloc_out(self, frames: int):
+        import torch
+        if self.output == "fir":
+            dt = torch.complex64 if self.complex_input else torch.float32
+        else:
+            dt = torch.complex64
+        return torch.empty((frames, self.channels_out), dtype=dt, device=f"cuda:{self.device}")
+
+    def execute(self, x, out=None, state: "State | None" = None, stream=None):
+        """Run on a 1-D device tensor x (float32 or complex64); returns the
+        output tensor (frames x channels_out)."""
+        import torch
+        want = torch.complex64 if self.complex_input else torch.float32
+        if x.dtype != want or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"input must be a contiguous 1-D {want} CUDA tensor")
+        n = x.numel()
+        frames = self.output_frames(n, state)
+        if out is None:
+            out = self.alloc_out(frames)
+        cap = out.shape[0] if out.dim() == 2 and out.shape[1] == self.channels_out else 0
+        fw = ctypes.c_int64()
+        check(load().tina_pfb_execute(self.handle, ctypes.c_void_p(x.data_ptr() if n else 0), n,
+                                      ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap,
+                                      state.handle if state else None, ctypes.byref(fw), _stream_handle(stream)))
+        return out[: fw.value]
+
+    __call__ = execute
+
+
+class State:
+    """Per-stream filter state (history and residue) on the device."""
+
+    def __init__(self, plan: Plan):
+        self.plan = plan
+        h = ctypes.c_void_p()
+        check(load().tina_pfb_state_create(plan.handle, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tina_pfb_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        check(load().tina_pfb_state_reset(self.handle))
+
+    def size(self):
+        n, r = ctypes.c_int64(), ctypes.c_int64()
+        check(load().tina_pfb_state_size(self.handle, ctypes.byref(n), ctypes.byref(r)))
+        return n.value, r.value
+
+    def export(self) -> np.ndarray:
+        n, _ = self.size()
+        dt = np.complex64 if self.plan.complex_input else np.float32
+        buf = np.empty(n, dtype=dt)
+        got = ctypes.c_int64()
+        check(load().tina_pfb_state_export(self.handle, buf.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(got)))
+        return buf[: got.value]
+
+    def load_from(self, buf: np.ndarray):
+        dt = np.complex64 if self.plan.complex_input else np.float32
+        b = np.ascontiguousarray(buf, dtype=dt)
+        check(load().tina_pfb_state_import(self.handle, b.ctypes.data_as(ctypes.c_void_p), b.size))

@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every function the public headers
+declare; argument validation that happens before any device call works on
+the CPU.  No compute calls (there is no GPU here)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(tina_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2408_16551_amd import pfb
+    if not os.path.exists(pfb.LIB_PATH):
+        pytest.fail("libtina_pfb.so not built (run __graft_entry__.build())")
+    return pfb.load()
+
+
+def test_headers_declare_the_boundary():
+    names = _declared()
+    for required in ("tina_pfb_plan", "tina_pfb_execute", "tina_pfb_state_create", "tina_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_binding_lists_every_declared_symbol():
+    from paper_2408_16551_amd import pfb
+    assert set(_declared()) <= set(pfb.EXPORTS)
+
+
+def _desc(pfb, **kw):
+    d = pfb._Desc()
+    d.struct_size = ctypes.sizeof(pfb._Desc)
+    d.channels, d.taps, d.sample_type, d.window, d.precision, d.output, d.device = 1024, 16, 0, 1, 0, 0, 0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({"channels": 1000}, 2), ({"channels": 8}, 2), ({"channels": 16384}, 2), ({"taps": 65}, 2),
+    ({"taps": 0}, 1), ({"channels": -4}, 1), ({"sample_type": 7}, 1), ({"window": 9}, 1),
+    ({"precision": 9}, 1), ({"output": 5}, 1), ({"window": 4}, 1), ({"struct_size": 4}, 1),
+])
+def test_plan_rejects_bad_descriptors_before_device(lib, kw, status):
+    from paper_2408_16551_amd import pfb
+    d = _desc(pfb, **kw)
+    h = ctypes.c_void_p()
+    assert lib.tina_pfb_plan(ctypes.byref(d), ctypes.byref(h)) == status
+    assert not h.value
+    assert lib.tina_last_error().decode()
+
+
+def test_null_arguments_rejected(lib):
+    h = ctypes.c_void_p()
+    assert lib.tina_pfb_plan(None, ctypes.byref(h)) == 1
+    fw = ctypes.c_int64()
+    assert lib.tina_pfb_execute(None, None, 0, None, 0, None, ctypes.byref(fw), None) == 1
+    assert lib.tina_pfb_state_create(None, ctypes.byref(h)) == 1
+    assert lib.tina_pfb_channels_out(None, None) == 1
+    assert lib.tina_pfb_plan_destroy(None) == 0
+    assert lib.tina_pfb_state_destroy(None) == 0
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.tina_version()
