@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X filter bank.
+
+One step = one tina_pfb_execute over the whole real stream (1024 channels,
+16 taps, sinc x Hann, 2^26 float32 samples, noise + 8 tones, DFT as FP32
+GEMM): the polyphase FIR kernel then the DFT-GEMM kernel, input resident in
+HBM.  Prints ONE JSON line with the throughput (input GSamples/s), the
+roofline of the dominant kernel (HIP events on the launch stream, inside the
+timed region), the other precision forms with their error against the FP64
+oracle, and the oracle itself timed on the host cores on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp16": 2500.0, "fp16x3": 2500.0, "fp8": 5000.0}
+PEAK_HBM_GBS = 8000.0
+MFMA_FLOP_MULT = {"fp32": 1, "bf16": 1, "fp16": 1, "bf16x3": 3, "fp16x3": 3, "fp8": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def dft_flops_per_frame(P: int, cplx: bool) -> float:
+    """Algorithmic flops of the dense DFT of one frame as the GEMM computes it:
+    real frame P x P real products (the two identically-zero imaginary
+    channels excluded), complex frame 2P x 2P."""
+    return 2.0 * (2 * P) * (2 * P) if cplx else 2.0 * P * P
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_2408_16551_amd/csrc/gemm.hip", "paper_2408_16551_amd/csrc/internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per DFT-GEMM launch from the committed rocprofv3 counter
+    summary, or None if it is missing or was taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", f"dft_gemm_fp32_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_steps(plan, xd, out, steps, warmup, torch):
+    for _ in range(warmup):
+        plan(xd, out=out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan(xd, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fir_ms, nf, dft_ms, nd = plan.profile_read()
+    plan.profile(False)
+    return (t1 - t0) / steps, fir_ms / max(nf, 1), dft_ms / max(nd, 1)
+
+
+def sampled_frames(F, M, n, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    fr = set(range(min(F, M + 1))) | {F - 1}
+    fr |= set(g.choice(F, size=min(F, n), replace=False).tolist())
+    return np.array(sorted(fr), dtype=np.int64)
+
+
+def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
+    """Throughput and error of each precision form on workload w."""
+    from paper_2408_16551_amd.pfb import Plan
+    xd = torch.from_numpy(w.x).cuda()
+    N = w.x.size
+    F = N // w.P
+    fr = sampled_frames(F, w.M, n_frames_err, seed=7)
+    ref = oracle_obj.pfb(w.x, w.P, w.M, oracle_obj.window(w.P, w.M, w.window), frames=fr)
+    res = {}
+    for form in forms:
+        plan = Plan(w.P, w.M, "c64" if w.complex_input else "r32", w.window, form, "pfb")
+        out = plan.alloc_out(F)
+        sec, fir_ms, dft_ms = timed_steps(plan, xd, out, steps, warmup, torch)
+        got = out[torch.from_numpy(fr).cuda()].cpu().numpy()
+        flops = dft_flops_per_frame(w.P, w.complex_input) * F
+        res[form] = {
+            "gsps": round(N / sec / 1e9, 3),
+            "ms_per_step": round(sec * 1e3, 4),
+            "rel_l2_vs_fp64_oracle": float(f"{rel_l2(got, ref):.3e}"),
+            "dft_ms": round(dft_ms, 4), "fir_ms": round(fir_ms, 4),
+            "dft_useful_tflops": round(flops / (dft_ms * 1e-3) / 1e12, 2),
+            "dft_mfma_frac": round(flops * MFMA_FLOP_MULT[form] / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS[form], 4),
+        }
+        log(f"[bench] {w.name} {form}: {res[form]}")
+        plan.close()
+        del out
+    return res
+
+
+def cpu_baseline(w, target_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of frames."""
+    from oracle import Oracle
+    o = Oracle()
+    h = o.window(w.P, w.M, w.window)
+    F = w.x.size // w.P
+    # Double the sample until a run lasts a tenth of the target, then scale to it.
+    n, dt = 16, 0.0
+    while n < F:
+        t = time.perf_counter()
+        o.pfb(w.x, w.P, w.M, h, frames=np.arange(n, dtype=np.int64))
+        dt = time.perf_counter() - t
+        if dt >= target_s / 10:
+            break
+        n *= 2
+    n = int(min(F, max(n, n * target_s / max(dt, 1e-9))))
+    t = time.perf_counter()
+    o.pfb(w.x, w.P, w.M, h, frames=np.arange(n, dtype=np.int64))
+    dt = time.perf_counter() - t
+    return {"value": round(n * w.P / dt / 1e9, 6), "unit": "GSamples/s", "cores": o.threads(), "kind": "oracle",
+            "sample": f"first {n} of {F} frames ({n * w.P} input samples) of {w.name}, FP64 direct FIR + "
+                      f"direct-sum DFT, {dt:.1f} s wall on {o.threads()} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
+                 "(--gpus must be 1); see DESIGN.md for how the filter bank would shard.")
+
+    import torch
+
+    from paper_2408_16551_amd import workloads
+    from paper_2408_16551_amd.pfb import Plan
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 3 x (read 1 GiB + write 1 GiB)")
+        return
+
+    log("[bench] generating the real stream workload")
+    w = workloads.real_stream()
+    N = w.x.size
+    F = N // w.P
+    xd = torch.from_numpy(w.x).cuda()
+    plan = Plan(w.P, w.M, "r32", w.window, "fp32", "pfb")
+    out = plan.alloc_out(F)
+    log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up steps")
+    sec, fir_ms, dft_ms = timed_steps(plan, xd, out, args.steps, args.warmup, torch)
+    gsps = N / sec / 1e9
+    flops = dft_flops_per_frame(w.P, False) * F
+    achieved = flops / (dft_ms * 1e-3) / 1e12
+    traffic = read_traffic(w.name)
+    fir_bytes = 4.0 * N + 4.0 * F * w.P      # algorithmic: read input, write FIR output
+    result = {
+        "metric": "PFB input GSamples/s (FP32 DFT GEMM; reduced-precision forms at their rel. error in 'forms')",
+        "value": round(gsps, 3),
+        "unit": "GSamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded N(0,1) noise + 8 channel-centre tones)",
+        "config": {"workload": w.name, "channels": w.P, "taps": w.M, "window": "sinc x hann",
+                   "samples": N, "sample_type": "r32", "precision": "fp32"},
+        "roofline": {"kernel": "dft_gemm_kernel<FP32>", "bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": traffic,
+                     "flops_per_launch": flops, "avg_launch_ms": round(dft_ms, 4)},
+        "stages": {"fir": {"kernel": "fir_kernel", "bound": "hbm", "avg_launch_ms": round(fir_ms, 4),
+                           "achieved": round(fir_bytes / (fir_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": round(fir_bytes / (fir_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "bytes_per_launch": fir_bytes}},
+    }
+    del out
+    plan.close()
+
+    if not args.no_forms:
+        from oracle import Oracle
+        o = Oracle()
+        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8"]
+        result["forms"] = {w.name: forms_table(w, forms, max(5, args.steps // 2), 2, torch, o, 24)}
+        del xd
+        wd = workloads.wide_dynamic_range()
+        result["forms"][wd.name] = forms_table(wd, forms, 5, 2, torch, o, 12)
+        del wd
+        # FIR-only path on the real stream (the stage the FIR roofline measures).
+        fplan = Plan(w.P, w.M, "r32", w.window, "fp32", "fir")
+        xd = torch.from_numpy(w.x).cuda()
+        fout = fplan.alloc_out(F)
+        s2, f2, _ = timed_steps(fplan, xd, fout, args.steps, 3, torch)
+        result["fir_only"] = {"gsps": round(N / s2 / 1e9, 2), "kernel_ms": round(f2, 4),
+                              "hbm_gbs": round(fir_bytes / (f2 * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(fir_bytes / (f2 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        del fout, xd
+        fplan.close()
+
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host (bounded sample)")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

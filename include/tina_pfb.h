@@ -120,9 +120,9 @@ const char* tina_version(void);
  * Create a plan: designs the prototype window and the DFT operand (the
  * Fourier matrix of Sec. 4.1 in the operand form of the chosen precision) on
  * the device in FP64, then rounds them to the forms the kernels use.  The
- * plan owns all of its device memory, including a workspace sized for
- * `max_chunk_frames`-frame pieces (execute splits larger inputs), and
- * synchronises once before returning.
+ * plan owns all of its device memory, including a 512 MiB FP32 workspace
+ * for the FIR output (execute runs inputs with more frames than it holds
+ * as consecutive pieces), and synchronises once before returning.
  * Errors: INVALID_ARGUMENT (bad descriptor), UNSUPPORTED (P or M outside the
  * ranges above), OUT_OF_MEMORY, DEVICE.
  */
@@ -185,6 +185,18 @@ tina_status tina_pfb_state_export(tina_pfb_state_t state, void* host_buf, int64_
 /* Load a state exported by a plan with the same P, M and sample type:
  * n_samples = (M-1)*P + residue with 0 <= residue < P.  Synchronous. */
 tina_status tina_pfb_state_import(tina_pfb_state_t state, const void* host_buf, int64_t n_samples);
+
+/*
+ * Stage timing.  While enabled, tina_pfb_execute records a HIP event before
+ * and after each stage's kernel launch on the caller's stream (FIR stage;
+ * DFT-GEMM stage).  tina_pfb_profile_read waits for the recorded events and
+ * returns the summed kernel durations in milliseconds and the launch counts
+ * since the last enable; enabling again clears them.  Timing adds two event
+ * records per stage per execute; disable it for production runs.
+ */
+tina_status tina_pfb_profile_enable(tina_pfb_plan_t plan, int enable);
+tina_status tina_pfb_profile_read(tina_pfb_plan_t plan, double* fir_ms, int64_t* fir_launches,
+                                  double* dft_ms, int64_t* dft_launches);
 
 #ifdef __cplusplus
 }

@@ -11,44 +11,103 @@
 // columns, so each load and store of a frame row is contiguous across the wave.
 #include "internal.h"
 
+#include <stdio.h>
+#include <stdlib.h>
+
 namespace tina {
 namespace {
 
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
 template <int VEC> struct VecT;
 template <> struct VecT<1> { using T = float; };
-template <> struct VecT<2> { using T = float2; };
-template <> struct VecT<4> { using T = float4; };
+template <> struct VecT<2> { using T = fvec2; };
+template <> struct VecT<4> { using T = fvec4; };
 
 template <int VEC>
 __device__ inline float vget(const typename VecT<VEC>::T& v, int i) {
     if constexpr (VEC == 1) return v;
-    else if constexpr (VEC == 2) return i == 0 ? v.x : v.y;
-    else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+    else return v[i];
 }
 template <int VEC>
 __device__ inline void vset(typename VecT<VEC>::T& v, int i, float x) {
     if constexpr (VEC == 1) v = x;
-    else if constexpr (VEC == 2) { if (i == 0) v.x = x; else v.y = x; }
-    else { if (i == 0) v.x = x; else if (i == 1) v.y = x; else if (i == 2) v.z = x; else v.w = x; }
+    else v[i] = x;
 }
+
+template <bool NTL, class V>
+__device__ inline V ld(const V* p) {
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NTS, class V>
+__device__ inline void st(V* p, const V& v) {
+    if constexpr (NTS) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+__device__ __attribute__((aligned(16))) float kZeros[4] = {0.f, 0.f, 0.f, 0.f};
 
 // Input floats j0..j0+VEC-1 of frame g (g >= -(M-1)); ext = prefix ++ chunk,
 // frame g starting at ext float (g + M - 1) * W.  The VEC floats never
-// straddle the prefix/chunk boundary (plen is a multiple of VEC).
-template <int VEC>
+// straddle the prefix/chunk boundary (plen is a multiple of VEC).  The source
+// is chosen by a pointer select, not a branch, so that the loads of a block of
+// frames can all be in flight together.
+template <int VEC, bool NTL>
 __device__ inline typename VecT<VEC>::T load_frame(const FirArgs& a, int64_t g, int j0) {
     using V = typename VecT<VEC>::T;
     const int64_t e = (g + a.M - 1) * (int64_t)a.W + j0;
-    if (e >= a.plen) return *reinterpret_cast<const V*>(a.chunk + (e - a.plen));
-    if (a.prefix) return *reinterpret_cast<const V*>(a.prefix + e);
-    V z;
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) vset<VEC>(z, i, 0.0f);
-    return z;
+    const float* hist = a.prefix ? a.prefix + e : kZeros;
+    const float* p = e >= a.plen ? a.chunk + (e - a.plen) : hist;
+    return ld<NTL>(reinterpret_cast<const V*>(p));
 }
 
-// MT: ring length (unroll); EXACT: M == MT (no per-tap predicate).
-template <int VEC, int MT, bool EXACT, bool AMAX>
+// Taps of the VEC columns j0.. for tap m: h[(M-1-m)*P + (j0+v)/cf].
+template <int VEC>
+__device__ inline typename VecT<VEC>::T load_taps(const FirArgs& a, int M, int m, int j0) {
+    using V = typename VecT<VEC>::T;
+    const float* base = a.taps + (int64_t)(M - 1 - m) * a.P;
+    if (a.cf == 1) return *reinterpret_cast<const V*>(base + j0);
+    V t;
+    if constexpr (VEC == 4) {
+        const fvec2 v = *reinterpret_cast<const fvec2*>(base + (j0 >> 1));
+        t[0] = v[0]; t[1] = v[0]; t[2] = v[1]; t[3] = v[1];
+    } else if constexpr (VEC == 2) {
+        const float v = base[j0 >> 1];
+        t[0] = v; t[1] = v;
+    } else {
+        t = base[j0 >> 1];
+    }
+    return t;
+}
+
+// One output frame from ring slot u (the newest frame) and the MT-1 before it.
+template <int VEC, int MT, bool EXACT>
+__device__ __forceinline__ typename VecT<VEC>::T fir_point(const typename VecT<VEC>::T (&tp)[MT],
+                                                           const typename VecT<VEC>::T (&win)[MT], int u, int M) {
+    typename VecT<VEC>::T acc = tp[0] * win[u];
+#pragma unroll
+    for (int m = 1; m < MT; ++m) {
+        if (EXACT || m < M) acc = __builtin_elementwise_fma(tp[m], win[(u - m + MT) % MT], acc);
+    }
+    return acc;
+}
+
+template <int VEC, bool AMAX>
+__device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
+                                         int gw) {
+    if constexpr (AMAX) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
+        for (int off = gw >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, gw));
+        if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
+    }
+}
+
+// MT: ring length (unroll); EXACT: M == MT (no per-tap predicate);
+// NT: non-temporal input loads and output stores (streaming cache policy).
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT>
 __global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
     using V = typename VecT<VEC>::T;
     const int ct = a.W / VEC;                    // threads per frame row (power of two)
@@ -62,66 +121,84 @@ __global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
     const int64_t f_end = min(a.F, f_begin + TF);
     const int j0 = col * VEC;
     const int M = EXACT ? MT : a.M;
+    const int gw = ct < 64 ? ct : 64;            // lanes sharing one frame row in a wave
 
-    float tp[MT][VEC];
+    V tp[MT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v)
-            tp[m][v] = (EXACT || m < M) ? a.taps[(int64_t)(M - 1 - m) * a.P + (j0 + v) / a.cf] : 0.0f;
+    for (int m = 0; m < MT; ++m) tp[m] = (EXACT || m < M) ? load_taps<VEC>(a, M, m, j0) : V(0.0f);
 
     V win[MT];
     // Frames f_begin - d (d = 1..M-1) go to ring slot MT - d (f_begin is a multiple of MT).
 #pragma unroll
     for (int d = 1; d < MT; ++d) {
-        if (EXACT || d < M) win[MT - d] = load_frame<VEC>(a, a.g0 + f_begin - d, j0);
+        win[MT - d] = (EXACT || d < M) ? load_frame<VEC, false>(a, a.g0 + f_begin - d, j0) : V(0.0f);
     }
+    win[0] = V(0.0f);
 
-    const int gw = ct < 64 ? ct : 64;            // lanes sharing one frame row in a wave
-    for (int64_t fb = f_begin; fb < f_end; fb += MT) {
+    // Full blocks of MT frames, loaded SB frames at a time: the SB loads of a
+    // sub-block issue before its first FMA.
+    constexpr int SB = (VEC == 4 ? 8 : 16) < MT ? (VEC == 4 ? 8 : 16) : MT;
+    int64_t fb = f_begin;
+    for (; fb + MT <= f_end; fb += MT) {
 #pragma unroll
-        for (int u = 0; u < MT; ++u) {
-            const int64_t f = fb + u;
-            if (f < f_end) {
-                win[u] = load_frame<VEC>(a, a.g0 + f, j0);
-                V acc;
+        for (int sb = 0; sb < MT; sb += SB) {
+            V in[SB];
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    float s = 0.0f;
+            for (int i = 0; i < SB; ++i) in[i] = load_frame<VEC, NT>(a, a.g0 + fb + sb + i, j0);
 #pragma unroll
-                    for (int m = 0; m < MT; ++m) {
-                        if (EXACT || m < M) s = fmaf(tp[m][v], vget<VEC>(win[(u - m + MT) % MT], v), s);
-                    }
-                    vset<VEC>(acc, v, s);
-                }
-                *reinterpret_cast<V*>(a.y + f * a.ldy + j0) = acc;
-                if constexpr (AMAX) {
-                    float mx = 0.0f;
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
-                    for (int off = gw >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, gw));
-                    if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
-                }
+            for (int i = 0; i < SB; ++i) {
+                const int u = sb + i;
+                win[u] = in[i];
+                const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
+                st<NT>(reinterpret_cast<V*>(a.y + (fb + u) * a.ldy + j0), acc);
+                fir_amax<VEC, AMAX>(a, acc, fb + u, col, gw);
             }
         }
     }
+    // Tail block.
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+        if (fb + u < f_end) {
+            win[u] = load_frame<VEC, NT>(a, a.g0 + fb + u, j0);
+            const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
+            st<NT>(reinterpret_cast<V*>(a.y + (fb + u) * a.ldy + j0), acc);
+            fir_amax<VEC, AMAX>(a, acc, fb + u, col, gw);
+        }
+    }
+}
+
+// Launch-shape override for tuning sweeps: TINA_FIR_TUNE="vec,tf,nt"
+// (vec 0 and tf 0 keep the defaults; nt 0 turns non-temporal access off).
+struct FirTune { int vec = 0, tf = 0, nt = -1; };
+FirTune fir_tune() {
+    static FirTune t = [] {
+        FirTune r;
+        if (const char* e = getenv("TINA_FIR_TUNE")) {
+            int v = 0, f = 0, n = -1;
+            if (sscanf(e, "%d,%d,%d", &v, &f, &n) >= 1) { r.vec = v; r.tf = f; r.nt = n; }
+        }
+        return r;
+    }();
+    return t;
 }
 
 template <int VEC, int MT, bool EXACT, bool AMAX>
 hipError_t launch_one(FirArgs& a, hipStream_t s) {
     const int ct = a.W / VEC;
-    // Frames per thread: a multiple of MT; long enough that the (M-1)-frame
-    // halo is a small fraction, short enough to leave many waves in flight.
-    int TF = MT;
-    while (TF < 32) TF += MT;
-    int64_t runs = (a.F + TF - 1) / TF;
-    while (TF < 128 && runs * ct > 256 * 1024) {
-        TF += MT;
-        runs = (a.F + TF - 1) / TF;
-    }
+    // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
+    // least 16) keeps the halo re-reads in L2 while leaving enough waves to
+    // hide HBM latency.
+    int TF = 2 * MT < 16 ? 16 : 2 * MT;
+    const FirTune tune = fir_tune();
+    if (tune.tf > 0) TF = ((tune.tf + MT - 1) / MT) * MT;
+    const int64_t runs = (a.F + TF - 1) / TF;
     const int64_t threads = runs * ct;
     const int64_t blocks = (threads + 255) / 256;
-    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
+    // Non-temporal loads and stores by default (streaming data, measured faster).
+    if (tune.nt != 0)
+        hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, true>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
+    else
+        hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, false>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
     return hipGetLastError();
 }
 
@@ -150,7 +227,11 @@ hipError_t launch_vec(FirArgs& a, hipStream_t s) {
 
 int pick_vec(const FirArgs& a) {
     auto aligned = [](const void* p, int bytes) { return ((uintptr_t)p % bytes) == 0; };
-    int vec = a.M <= 16 ? 4 : (a.M <= 32 ? 2 : 1);
+    // Vector width by register budget (taps, ring and prefetch each take
+    // MT*VEC registers): 4 floats for up to 8 taps, else 1 (measured best).
+    int vec = a.M <= 8 ? 4 : 1;
+    const FirTune tune = fir_tune();
+    if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec < vec ? tune.vec : vec;
     while (vec > 1 && !(a.plen % vec == 0 && aligned(a.chunk, 4 * vec) && aligned(a.y, 4 * vec) &&
                         (a.prefix == nullptr || aligned(a.prefix, 4 * vec)) && a.ldy % vec == 0))
         vec >>= 1;

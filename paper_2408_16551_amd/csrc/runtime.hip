@@ -14,6 +14,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "tina_pfb.h"
@@ -67,8 +68,30 @@ struct tina_pfb_plan_s {
     float* amax = nullptr;
     int64_t ch_frames = 0;
     int64_t amax_parts_cap = 0;
+    // Stage timing (tina_pfb_profile_*): recorded event pairs per stage.
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fir, ev_dft;
+
+    hipEvent_t next_event() {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    void clear_events() {
+        ev_used = 0;
+        ev_fir.clear();
+        ev_dft.clear();
+    }
 
     void release() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        ev_pool.clear();
+        clear_events();
         for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax})
             if (p) (void)hipFree(p);
         h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr;
@@ -231,13 +254,29 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     fa.M = p->M;
     fa.cf = p->cf;
 
+    // Records a HIP event pair around one stage launch when profiling.
+    auto timed = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& list, auto&& launch) -> hipError_t {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p->profiling) {
+            e0 = p->next_event();
+            e1 = p->next_event();
+            if (e0 && e1) (void)hipEventRecord(e0, s);
+        }
+        hipError_t e = launch();
+        if (e == hipSuccess && e0 && e1) {
+            e = hipEventRecord(e1, s);
+            list.emplace_back(e0, e1);
+        }
+        return e;
+    };
+
     if (p->output == TINA_OUT_FIR_ONLY) {
         fa.y = (float*)d_out;
         fa.ldy = p->W;
         fa.g0 = 0;
         fa.F = F;
         fa.amax = nullptr;
-        HIP_TRY(launch_fir(fa, s));
+        if (F > 0) HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
     } else {
         const int form = p->precision;
         const int64_t ldo = p->cf == 2 ? 2 * (int64_t)p->P : (int64_t)p->P + 2;
@@ -248,7 +287,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.g0 = c0;
             fa.F = Fc;
             fa.amax = form_scaled(form) ? p->amax : nullptr;
-            HIP_TRY(launch_fir(fa, s));
+            HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
             GemmArgs ga{};
             ga.A = p->ws;
             ga.lda = p->W;
@@ -263,7 +302,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             ga.N = p->N;
             ga.real_pack = p->cf == 1;
             ga.form = form;
-            HIP_TRY(launch_dft_gemm(ga, s));
+            HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
     }
     if (st) {
@@ -275,6 +314,35 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     }
     if (frames_written) *frames_written = F;
     return TINA_OK;
+}
+
+tina_status tina_pfb_profile_enable(tina_pfb_plan_t p, int enable) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "profile_enable: NULL plan");
+    DeviceScope ds(p->device);
+    HIP_TRY(hipDeviceSynchronize());
+    p->clear_events();
+    p->profiling = enable != 0;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_profile_read(tina_pfb_plan_t p, double* fir_ms, int64_t* fir_n, double* dft_ms, int64_t* dft_n) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "profile_read: NULL plan");
+    DeviceScope ds(p->device);
+    auto sum = [&](const std::vector<std::pair<hipEvent_t, hipEvent_t>>& list, double* ms, int64_t* n) -> tina_status {
+        double t = 0.0;
+        for (const auto& pr : list) {
+            HIP_TRY(hipEventSynchronize(pr.second));
+            float x = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&x, pr.first, pr.second));
+            t += x;
+        }
+        if (ms) *ms = t;
+        if (n) *n = (int64_t)list.size();
+        return TINA_OK;
+    };
+    tina_status st = sum(p->ev_fir, fir_ms, fir_n);
+    if (st != TINA_OK) return st;
+    return sum(p->ev_dft, dft_ms, dft_n);
 }
 
 tina_status tina_pfb_state_create(tina_pfb_plan_t p, tina_pfb_state_t* out) {

@@ -29,6 +29,7 @@ EXPORTS = [
     "tina_pfb_output_frames", "tina_pfb_execute",
     "tina_pfb_state_create", "tina_pfb_state_destroy", "tina_pfb_state_reset", "tina_pfb_state_size",
     "tina_pfb_state_export", "tina_pfb_state_import",
+    "tina_pfb_profile_enable", "tina_pfb_profile_read",
 ]
 
 
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH):
         "tina_pfb_state_size": ([vp, P64, P64], i32),
         "tina_pfb_state_export": ([vp, vp, i64, P64], i32),
         "tina_pfb_state_import": ([vp, vp, i64], i32),
+        "tina_pfb_profile_enable": ([vp, i32], i32),
+        "tina_pfb_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), P64, ctypes.POINTER(ctypes.c_double), P64], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -130,6 +133,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable: bool = True):
+        """Enable (and clear) or disable per-stage HIP-event timing."""
+        check(load().tina_pfb_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        """(fir_ms_total, fir_launches, dft_ms_total, dft_launches) since enable."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        check(load().tina_pfb_profile_read(self.handle, ctypes.byref(a), ctypes.byref(na), ctypes.byref(b),
+                                           ctypes.byref(nb)))
+        return a.value, na.value, b.value, nb.value
 
     def taps(self) -> np.ndarray:
         h = np.empty(self.P * self.M, dtype=np.float64)
