@@ -1,0 +1,457 @@
+// Batched execution of many stream chunks with different channel counts,
+// tap counts and lengths in one persistent launch per stage:
+//   FIR stage  -> fir_batch_kernel   (all items' FIR units)
+//   DFT stage  -> dft_gemm_batch_kernel (all items' GEMM tiles)
+//   state      -> gather_batch_kernel (all items' history/residue updates)
+// The launches read a device-resident BatchTable (item arguments, first unit
+// of each item per stage, and a cost-balanced split of every stage's units
+// into one contiguous range per XCD).  The table is uploaded from pinned host
+// memory on the caller's stream before the launches, so the launch arguments
+// themselves never change; that also makes the three launches capturable in
+// a graph and replayable with a new table.
+//
+// Launch shapes (frames per FIR thread, GEMM blocks per CU) are chosen by a
+// small autotuner on the batch's own shape and cached by shape signature,
+// in memory and, when TINA_TUNE_CACHE names a file, on disk.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "runtime_types.h"
+#include "tina_pfb_batch.h"
+
+using namespace tina;
+
+namespace {
+
+struct Tune {
+    int fir_tf_mult = 2;      // frames per FIR thread = mult * MT
+    int gemm_blocks_per_cu = 2;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune_cache;
+bool g_tune_loaded = false;
+
+const char* tune_path() { return getenv("TINA_TUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* p = tune_path();
+    if (!p) return;
+    FILE* f = fopen(p, "r");
+    if (!f) return;
+    char key[512];
+    int a, b;
+    while (fscanf(f, "%511s %d %d", key, &a, &b) == 3) g_tune_cache[key] = Tune{a, b};
+    fclose(f);
+}
+
+void tune_store_locked() {
+    const char* p = tune_path();
+    if (!p) return;
+    FILE* f = fopen(p, "w");
+    if (!f) return;
+    for (const auto& kv : g_tune_cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.fir_tf_mult, kv.second.gemm_blocks_per_cu);
+    fclose(f);
+}
+
+int pow2_at_least(int m) {
+    int t = 1;
+    while (t < m) t <<= 1;
+    return t;
+}
+
+}  // namespace
+
+struct tina_pfb_batch_s {
+    int device = 0;
+    int form = 0;
+    int max_items = 0;
+    int cus = 256;
+    float* ws = nullptr;         // FIR output of all items
+    int64_t ws_floats = 0;
+    float* amax = nullptr;       // per-frame partial maxima (scaled forms)
+    int64_t amax_floats = 0;
+    BatchTable* d_table = nullptr;
+    BatchTable* h_table = nullptr;  // pinned
+    size_t table_bytes = 0;
+    hipEvent_t table_free = nullptr;  // the last upload from h_table has completed
+    bool table_pending = false;
+    Tune tune;
+    bool have_tune = false;
+
+    void release() {
+        if (table_free) (void)hipEventDestroy(table_free);
+        if (h_table) (void)hipHostFree(h_table);
+        for (void* p : {(void*)ws, (void*)amax, (void*)d_table})
+            if (p) (void)hipFree(p);
+        table_free = nullptr; h_table = nullptr; ws = nullptr; amax = nullptr; d_table = nullptr;
+    }
+};
+
+namespace {
+
+size_t table_size(int n) { return sizeof(BatchTable) + sizeof(BatchItem) * (size_t)(n > 1 ? n - 1 : 0); }
+
+// Cost-balanced split of a stage's units into 8 contiguous ranges: item i has
+// units[i] units of cost cost[i] each.
+void split_by_cost(const std::vector<int64_t>& units, const std::vector<double>& cost, int64_t (&bounds)[9]) {
+    double total = 0.0;
+    int64_t total_units = 0;
+    for (size_t i = 0; i < units.size(); ++i) {
+        total += (double)units[i] * cost[i];
+        total_units += units[i];
+    }
+    int64_t u0 = 0;
+    double c0 = 0.0;
+    bounds[0] = 0;
+    int x = 1;
+    for (size_t i = 0; i < units.size() && x < 8; ++i) {
+        const double ci = (double)units[i] * cost[i];
+        while (x < 8 && c0 + ci >= total * x / 8.0) {
+            const double need = total * x / 8.0 - c0;
+            int64_t k = cost[i] > 0 ? (int64_t)(need / cost[i] + 0.5) : 0;
+            k = std::max<int64_t>(0, std::min<int64_t>(k, units[i]));
+            bounds[x] = std::max(bounds[x - 1], u0 + k);
+            ++x;
+        }
+        u0 += units[i];
+        c0 += ci;
+    }
+    for (; x < 8; ++x) bounds[x] = std::max(bounds[x - 1], std::min(u0, total_units));
+    bounds[8] = total_units;  // every unit belongs to exactly one range
+}
+
+struct GroupPlan {
+    int first, count;  // items [first, first + count)
+};
+
+// Validates the work items against the batch and returns the frame count of each.
+tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vector<int64_t>& frames) {
+    if (n < 0 || n > b->max_items) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: item count outside [0, max_items]");
+    if (n > 0 && !w) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: NULL item array");
+    frames.assign(n, 0);
+    std::vector<const void*> states;
+    for (int i = 0; i < n; ++i) {
+        const tina_pfb_work& it = w[i];
+        const tina_pfb_plan_s* p = it.plan;
+        if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: item " + std::to_string(i) + " has no plan");
+        if (p->device != b->device) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: plan on another device");
+        if (p->output != TINA_OUT_PFB || p->precision != b->form)
+            return fail(TINA_ERR_INVALID_ARGUMENT, "batch: every plan must be a filter-bank plan of the batch's precision");
+        if (it.n_samples < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: negative sample count");
+        if (it.n_samples > 0 && !it.d_in) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: NULL input");
+        if ((uintptr_t)it.d_in % (p->cf * sizeof(float))) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: input misaligned");
+        if ((uintptr_t)it.d_out % 8) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: output misaligned");
+        if (it.state && it.state->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: state belongs to another plan");
+        if (it.state) {
+            if (std::find(states.begin(), states.end(), (const void*)it.state) != states.end())
+                return fail(TINA_ERR_INVALID_ARGUMENT, "batch: a state appears twice in one batch");
+            states.push_back(it.state);
+        }
+        const int64_t r = it.state ? it.state->residue : 0;
+        frames[i] = (r + it.n_samples) / p->P;
+        if (frames[i] > 0 && !it.d_out) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: NULL output");
+        if (frames[i] > it.out_capacity_frames)
+            return fail(TINA_ERR_INVALID_ARGUMENT, "batch: item " + std::to_string(i) + " output capacity below its frame count");
+        if (frames[i] * (int64_t)p->W > b->ws_floats)
+            return fail(TINA_ERR_TOO_LARGE, "batch: item " + std::to_string(i) + " alone exceeds the batch workspace");
+    }
+    return TINA_OK;
+}
+
+// Fills the host table for items [g.first, g.first + g.count) and returns the
+// launch parameters.  `dry` leaves state updates out (tuning runs).
+void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, const GroupPlan& g,
+                const Tune& tune, bool dry, int& max_m, bool& all_exact) {
+    BatchTable* t = b->h_table;
+    t->n_items = g.count;
+    max_m = 1;
+    for (int i = 0; i < g.count; ++i) max_m = std::max(max_m, w[g.first + i].plan->M);
+    const int MT = pow2_at_least(max_m);
+    all_exact = true;
+    for (int i = 0; i < g.count; ++i) all_exact = all_exact && w[g.first + i].plan->M == MT;
+    const int TF = tune.fir_tf_mult * MT < 16 ? ((16 + MT - 1) / MT) * MT : tune.fir_tf_mult * MT;
+
+    std::vector<int64_t> fu(g.count), gu(g.count), su(g.count);
+    std::vector<double> fc(g.count), gc(g.count), sc(g.count, 1.0);
+    int64_t ws_off = 0, amax_off = 0, f0 = 0, g0 = 0, s0 = 0;
+    for (int i = 0; i < g.count; ++i) {
+        tina_pfb_work& it = w[g.first + i];
+        tina_pfb_plan_s* p = it.plan;
+        tina_pfb_state_s* st = it.state;
+        BatchItem& bi = t->items[i];
+        memset(&bi, 0, sizeof(bi));
+        const int64_t F = frames[g.first + i];
+        const int64_t r = st ? st->residue : 0;
+        FirArgs& fa = bi.fir;
+        fa.prefix = st ? st->buf[st->cur] : nullptr;
+        fa.plen = (int64_t)(p->M - 1) * p->W + r * p->cf;
+        fa.chunk = (const float*)it.d_in;
+        fa.nchunk = it.n_samples * p->cf;
+        fa.taps = p->h32;
+        fa.y = b->ws + ws_off;
+        fa.ldy = p->W;
+        fa.g0 = 0;
+        fa.F = F;
+        fa.W = p->W;
+        fa.P = p->P;
+        fa.M = p->M;
+        fa.cf = p->cf;
+        fa.amax = form_scaled(b->form) ? b->amax + amax_off : nullptr;
+        fa.nparts = p->W >= 64 ? p->W / 64 : 1;  // VEC = 1 in the batched FIR
+        ws_off += F * p->W;
+        amax_off += F * fa.nparts;
+        GemmArgs& ga = bi.gemm;
+        ga.A = fa.y;
+        ga.lda = p->W;
+        ga.B0 = p->B[0];
+        ga.B1 = p->B[1];
+        ga.amax = fa.amax;
+        ga.nparts = fa.nparts;
+        ga.out = (float*)it.d_out;
+        ga.ldo = p->cf == 2 ? 2 * (int64_t)p->P : (int64_t)p->P + 2;
+        ga.F = F;
+        ga.K = p->K;
+        ga.N = p->N;
+        ga.real_pack = p->cf == 1;
+        ga.form = b->form;
+        bi.fir_tf = TF;
+        const int64_t runs = (F + TF - 1) / TF;
+        fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
+        fc[i] = (double)TF * MT;
+        gu[i] = F > 0 ? ((F + kGemmBM - 1) / kGemmBM) * ((p->N + kGemmBN - 1) / kGemmBN) : 0;
+        gc[i] = (double)p->K;
+        bi.fir_unit0 = f0;
+        bi.gemm_unit0 = g0;
+        bi.st_unit0 = s0;
+        f0 += fu[i];
+        g0 += gu[i];
+        if (st && !dry) {
+            const int64_t r2 = (r + it.n_samples) % p->P;
+            bi.st_dst = st->buf[st->cur ^ 1];
+            bi.st_start = F * p->W;
+            bi.st_count = (int64_t)(p->M - 1) * p->W + r2 * p->cf;
+            su[i] = (bi.st_count + 255) / 256;
+        } else {
+            su[i] = 0;
+        }
+        s0 += su[i];
+    }
+    t->fir_units = f0;
+    t->gemm_units = g0;
+    t->st_units = s0;
+    split_by_cost(fu, fc, t->fir_bounds);
+    split_by_cost(gu, gc, t->gemm_bounds);
+    split_by_cost(su, sc, t->st_bounds);
+}
+
+// Groups items greedily so that each group's FIR output fits the workspace.
+std::vector<GroupPlan> make_groups(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, int n) {
+    std::vector<GroupPlan> gs;
+    int first = 0;
+    int64_t used = 0, used_amax = 0;
+    for (int i = 0; i < n; ++i) {
+        const tina_pfb_plan_s* p = w[i].plan;
+        const int64_t need = frames[i] * p->W;
+        const int64_t need_amax = frames[i] * (p->W >= 64 ? p->W / 64 : 1);
+        if (i > first && (used + need > b->ws_floats || (b->amax && used_amax + need_amax > b->amax_floats))) {
+            gs.push_back({first, i - first});
+            first = i;
+            used = 0;
+            used_amax = 0;
+        }
+        used += need;
+        used_amax += need_amax;
+    }
+    if (n > first) gs.push_back({first, n - first});
+    return gs;
+}
+
+tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, const Tune& tune, bool dry,
+                      const std::vector<int64_t>& frames) {
+    for (const GroupPlan& g : make_groups(b, w, frames, n)) {
+        if (b->table_pending) {
+            HIP_TRY(hipEventSynchronize(b->table_free));  // host copy of the table is free again
+            b->table_pending = false;
+        }
+        int max_m = 1;
+        bool all_exact = true;
+        fill_table(b, w, frames, g, tune, dry, max_m, all_exact);
+        const size_t bytes = table_size(g.count);
+        HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(b->table_free, s));
+        b->table_pending = true;
+        const int grid_fir = b->cus * 4;
+        const int grid_gemm = b->cus * tune.gemm_blocks_per_cu;
+        if (b->h_table->fir_units > 0)
+            HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), grid_fir, s));
+        if (b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, grid_gemm, s));
+        if (b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
+        if (!dry) {
+            for (int i = 0; i < g.count; ++i) {
+                tina_pfb_work& it = w[g.first + i];
+                it.frames_written = frames[g.first + i];
+                if (it.state) {
+                    it.state->cur ^= 1;
+                    it.state->residue = (it.state->residue + it.n_samples) % it.plan->P;
+                }
+            }
+        }
+    }
+    return TINA_OK;
+}
+
+std::string signature(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, int n) {
+    std::vector<std::string> parts;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        char buf[64];
+        snprintf(buf, sizeof buf, "%dx%dx%d", w[i].plan->P, w[i].plan->M, w[i].plan->cf);
+        parts.push_back(buf);
+        total += frames[i] * w[i].plan->P;
+    }
+    std::sort(parts.begin(), parts.end());
+    parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+    int lg = 0;
+    while ((1ll << (lg + 1)) <= total) ++lg;
+    std::string key = "form" + std::to_string(b->form) + ":s2^" + std::to_string(lg);
+    for (auto& p : parts) key += ":" + p;
+    return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+tina_status tina_pfb_batch_split_units(const int64_t* units, const double* cost, int32_t n, int64_t* bounds9) {
+    if (n < 0 || (n > 0 && (!units || !cost)) || !bounds9) return fail(TINA_ERR_INVALID_ARGUMENT, "split_units: NULL argument");
+    std::vector<int64_t> u(units, units + n);
+    std::vector<double> c(cost, cost + n);
+    int64_t b[9];
+    split_by_cost(u, c, b);
+    for (int i = 0; i < 9; ++i) bounds9[i] = b[i];
+    return TINA_OK;
+}
+
+tina_status tina_pfb_batch_create(int device, int precision, int max_items, int64_t workspace_bytes,
+                                  tina_pfb_batch_t* out) {
+    if (!out) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: NULL output handle");
+    *out = nullptr;
+    if (precision < TINA_PREC_FP32 || precision > TINA_PREC_FP8_FRAME)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: unknown precision");
+    if (max_items < 1 || max_items > 65536) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: max_items outside [1, 65536]");
+    if (workspace_bytes < (1 << 20)) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: workspace below 1 MiB");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: bad device");
+    DeviceScope ds(device);
+    tina_pfb_batch_s* b = new (std::nothrow) tina_pfb_batch_s();
+    if (!b) return fail(TINA_ERR_OUT_OF_MEMORY, "batch_create: host allocation");
+    b->device = device;
+    b->form = precision;
+    b->max_items = max_items;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        b->cus = ((prop.multiProcessorCount + 7) / 8) * 8;
+    b->ws_floats = workspace_bytes / 4;
+    b->table_bytes = table_size(max_items);
+    auto bail = [&](tina_status st, const char* m) {
+        b->release();
+        delete b;
+        return fail(st, m);
+    };
+    if (hipMalloc(&b->ws, b->ws_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: workspace");
+    if (form_scaled(precision)) {
+        b->amax_floats = b->ws_floats / 16 + 1024;  // F * max(1, W/64) <= F * W / 16 for W >= 16
+        if (hipMalloc(&b->amax, b->amax_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: scale workspace");
+    }
+    if (hipMalloc(&b->d_table, b->table_bytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: table");
+    if (hipHostMalloc(&b->h_table, b->table_bytes, hipHostMallocDefault) != hipSuccess)
+        return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: pinned table");
+    if (hipEventCreateWithFlags(&b->table_free, hipEventDisableTiming) != hipSuccess)
+        return bail(TINA_ERR_DEVICE, "batch_create: event");
+    *out = b;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_batch_destroy(tina_pfb_batch_t b) {
+    if (!b) return TINA_OK;
+    DeviceScope ds(b->device);
+    (void)hipDeviceSynchronize();
+    b->release();
+    delete b;
+    return TINA_OK;
+}
+
+tina_status tina_pfb_batch_execute(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n, void* stream) {
+    if (!b) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_execute: NULL batch");
+    std::vector<int64_t> frames;
+    tina_status st = validate(b, w, n, frames);
+    if (st != TINA_OK) return st;
+    DeviceScope ds(b->device);
+    Tune tune;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune_cache.find(signature(b, w, frames, n));
+        if (it != g_tune_cache.end()) tune = it->second;
+    }
+    return run_batch(b, w, n, (hipStream_t)stream, tune, false, frames);
+}
+
+tina_status tina_pfb_batch_tune(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n, void* stream,
+                                int32_t* fir_tf_mult, int32_t* gemm_blocks_per_cu) {
+    if (!b) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_tune: NULL batch");
+    std::vector<int64_t> frames;
+    tina_status st = validate(b, w, n, frames);
+    if (st != TINA_OK) return st;
+    DeviceScope ds(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int mults[] = {1, 2, 4};
+    const int bpcs[] = {1, 2};
+    Tune best;
+    float best_ms = 1e30f;
+    for (int m : mults)
+        for (int bpc : bpcs) {
+            Tune t{m, bpc};
+            st = run_batch(b, w, n, s, t, true, frames);  // warm-up, no state updates
+            if (st != TINA_OK) break;
+            HIP_TRY(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3 && st == TINA_OK; ++rep) st = run_batch(b, w, n, s, t, true, frames);
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (st == TINA_OK && ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TINA_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        g_tune_cache[signature(b, w, frames, n)] = best;
+        tune_store_locked();
+    }
+    if (fir_tf_mult) *fir_tf_mult = best.fir_tf_mult;
+    if (gemm_blocks_per_cu) *gemm_blocks_per_cu = best.gemm_blocks_per_cu;
+    return TINA_OK;
+}
+
+}  // extern "C"

@@ -14,6 +14,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 namespace tina {
 namespace {
 
@@ -107,13 +109,12 @@ __device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<V
 
 // MT: ring length (unroll); EXACT: M == MT (no per-tap predicate);
 // NT: non-temporal input loads and output stores (streaming cache policy).
+// One 256-thread unit of work: logical block `blk` of the (column, run) grid.
 template <int VEC, int MT, bool EXACT, bool AMAX, bool NT>
-__global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
+__device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) {
     using V = typename VecT<VEC>::T;
     const int ct = a.W / VEC;                    // threads per frame row (power of two)
-    const int64_t nb = gridDim.x;
-    const int64_t blk = xcd_logical_block(blockIdx.x, nb);
-    const int64_t gid = blk * blockDim.x + threadIdx.x;
+    const int64_t gid = blk * 256 + threadIdx.x;
     const int col = (int)(gid & (ct - 1));
     const int64_t run = gid / ct;
     const int64_t f_begin = run * TF;
@@ -164,6 +165,24 @@ __global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
             st<NT>(reinterpret_cast<V*>(a.y + (fb + u) * a.ldy + j0), acc);
             fir_amax<VEC, AMAX>(a, acc, fb + u, col, gw);
         }
+    }
+}
+
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT>
+__global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
+    fir_unit<VEC, MT, EXACT, AMAX, NT>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// Persistent batched FIR: each block walks its XCD's contiguous, cost-balanced
+// range of units (see BatchTable); a unit is one 256-thread block of one item.
+template <int MT, bool EXACT, bool AMAX>
+__global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __restrict__ t) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t end = t->fir_bounds[x + 1];
+    for (int64_t u = t->fir_bounds[x] + i; u < end; u += nbx) {
+        const int it = batch_find(t->items, t->n_items, u, /*stage=*/0);
+        const BatchItem& b = t->items[it];
+        fir_unit<1, MT, EXACT, AMAX, true>(b.fir, b.fir_tf, u - b.fir_unit0);
     }
 }
 
@@ -246,7 +265,27 @@ __global__ void gather_ext_kernel(const float* prefix, int64_t plen, const float
     dst[i] = e < plen ? (prefix ? prefix[e] : 0.0f) : chunk[e - plen];
 }
 
+// Batched state update: for every item with a state, dst[i] = ext[start + i].
+__global__ void gather_batch_kernel(const BatchTable* __restrict__ t) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t end = t->st_bounds[x + 1];
+    for (int64_t u = t->st_bounds[x] + i; u < end; u += nbx) {
+        const int it = batch_find(t->items, t->n_items, u, /*stage=*/2);
+        const BatchItem& b = t->items[it];
+        const int64_t k = (u - b.st_unit0) * 256 + threadIdx.x;
+        if (k < b.st_count) {
+            const int64_t e = b.st_start + k;
+            b.st_dst[k] = e < b.fir.plen ? (b.fir.prefix ? b.fir.prefix[e] : 0.0f) : b.fir.chunk[e - b.fir.plen];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(gather_batch_kernel, dim3(grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
 
 int fir_amax_parts(const FirArgs& a) {
     const int ct = a.W / pick_vec(a);
@@ -267,6 +306,28 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
         case 2: return launch_vec<2>(a, s);
         default: return launch_vec<1>(a, s);
     }
+}
+
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int grid, hipStream_t s) {
+    auto go = [&](auto mt_tag) -> hipError_t {
+        constexpr int MT = decltype(mt_tag)::value;
+        if (amax) {
+            if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, true>), dim3(grid), dim3(256), 0, s, t);
+            else hipLaunchKernelGGL((fir_batch_kernel<MT, false, true>), dim3(grid), dim3(256), 0, s, t);
+        } else {
+            if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, false>), dim3(grid), dim3(256), 0, s, t);
+            else hipLaunchKernelGGL((fir_batch_kernel<MT, false, false>), dim3(grid), dim3(256), 0, s, t);
+        }
+        return hipGetLastError();
+    };
+    if (max_m <= 1) return go(std::integral_constant<int, 1>{});
+    if (max_m <= 2) return go(std::integral_constant<int, 2>{});
+    if (max_m <= 4) return go(std::integral_constant<int, 4>{});
+    if (max_m <= 8) return go(std::integral_constant<int, 8>{});
+    if (max_m <= 16) return go(std::integral_constant<int, 16>{});
+    if (max_m <= 32) return go(std::integral_constant<int, 32>{});
+    if (max_m <= 64) return go(std::integral_constant<int, 64>{});
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_gather_ext(const float* prefix, int64_t plen, const float* chunk, int64_t nchunk,

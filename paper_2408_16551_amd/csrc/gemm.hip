@@ -99,7 +99,26 @@ __device__ inline void mfma_step(const uint4 (&a)[2][2], const uint4 (&b)[2][2],
 }
 
 template <int FORM>
-__global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
+struct GemmSmem {
+    static constexpr int NP = FT<FORM>::NP;
+    uint8_t tiles[2 * NP * BM * RS];  // NP A pieces then NP B pieces, BM (= BN) rows of RS bytes
+    float inv[BM], sc[BM];            // per-frame scale and its inverse
+};
+
+// Map a logical tile index L of an nm x nn grid: groups of GROUP_M m-tiles
+// sweep all n-tiles, so they share each B column block and their A rows.
+__device__ inline void grouped_tile(int64_t L, int64_t nm, int64_t nn, int64_t& m0, int64_t& n0) {
+    const int64_t gsz_full = GROUP_M * nn;
+    const int64_t grp = L / gsz_full, first_m = grp * GROUP_M;
+    const int64_t gsz = min((int64_t)GROUP_M, nm - first_m);
+    const int64_t within = L - grp * gsz_full;
+    m0 = (first_m + within % gsz) * BM;
+    n0 = (within / gsz) * BN;
+}
+
+// One BM x BN output tile at (m0, n0).  Called by every thread of the block.
+template <int FORM>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM>& sm) {
     using ft = FT<FORM>;
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
     constexpr int BK = ROWB / EB;                 // K elements per tile
@@ -109,25 +128,16 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     constexpr int NSLAB = ROWB / SLAB;
     constexpr int RD = SLAB / 32;                 // 16-byte reads per lane per slab
 
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * NP * BM * RS];
-    __shared__ float s_inv[BM], s_sc[BM];
-    uint8_t* As = smem;                 // NP pieces of BM x RS
-    uint8_t* Bs = smem + NP * BM * RS;  // NP pieces of BN x RS
+    uint8_t* As = sm.tiles;                 // NP pieces of BM x RS
+    uint8_t* Bs = sm.tiles + NP * BM * RS;  // NP pieces of BN x RS
+    float* s_inv = sm.inv;
+    float* s_sc = sm.sc;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 31, lh = lane >> 5;
 
-    // Tile of this block: XCD-aware, then grouped so that GROUP_M m-tiles
-    // share each n-tile of B while they share their A rows across n-tiles.
-    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
-    const int64_t L = xcd_logical_block(blockIdx.x, (int64_t)gridDim.x);
-    const int64_t gsz_full = GROUP_M * nn;
-    const int64_t grp = L / gsz_full, first_m = grp * GROUP_M;
-    const int64_t gsz = min((int64_t)GROUP_M, nm - first_m);
-    const int64_t within = L - grp * gsz_full;
-    const int64_t m0 = (first_m + within % gsz) * BM;
-    const int64_t n0 = (within / gsz) * BN;
+    __syncthreads();  // the previous tile of a persistent block is done with LDS
 
     if constexpr (ft::SCALED) {
         if (tid < BM) {
@@ -293,6 +303,32 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
 }
 
 template <int FORM>
+__global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) GemmSmem<FORM> sm;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, m0, n0);
+    gemm_tile<FORM>(g, m0, n0, sm);
+}
+
+// Persistent batched GEMM: each block walks its XCD's contiguous range of
+// tiles over all items (see BatchTable).
+template <int FORM>
+__global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __restrict__ t) {
+    __shared__ __attribute__((aligned(16))) GemmSmem<FORM> sm;
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t end = t->gemm_bounds[x + 1];
+    for (int64_t u = t->gemm_bounds[x] + i; u < end; u += nbx) {
+        const int it = batch_find(t->items, t->n_items, u, /*stage=*/1);
+        const GemmArgs& g = t->items[it].gemm;
+        const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+        int64_t m0, n0;
+        grouped_tile(u - t->items[it].gemm_unit0, nm, nn, m0, n0);
+        gemm_tile<FORM>(g, m0, n0, sm);
+    }
+}
+
+template <int FORM>
 hipError_t launch_form(const GemmArgs& g, hipStream_t s) {
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
     hipLaunchKernelGGL(dft_gemm_kernel<FORM>, dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
@@ -300,6 +336,19 @@ hipError_t launch_form(const GemmArgs& g, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_t s) {
+    switch (form) {
+        case FORM_FP32: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP32>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_BF16: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_BF16>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_BF16X3: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_BF16X3>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_FP16: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_FP16X3: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16X3>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_FP8: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP8>, dim3(grid), dim3(NT), 0, s, t); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
     if (g.F <= 0) return hipSuccess;

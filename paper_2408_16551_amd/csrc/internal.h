@@ -75,4 +75,49 @@ struct GemmArgs {
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
 
+// --------------------------------------------------------------- batched path
+// One item of a batched launch: the FIR and GEMM arguments of one stream
+// chunk, its first work unit in each stage, and its state update.
+struct BatchItem {
+    FirArgs fir;            // fir.y points into the batch workspace
+    GemmArgs gemm;          // gemm.A == fir.y
+    int64_t fir_unit0;      // first FIR unit (256-thread block) of this item
+    int64_t gemm_unit0;     // first GEMM tile of this item
+    int64_t st_unit0;       // first state-update unit
+    int32_t fir_tf;         // frames per FIR thread
+    int32_t pad_;
+    float* st_dst;          // state buffer to fill (nullptr: no state)
+    int64_t st_start, st_count;
+};
+
+// Device-resident table read by the persistent kernels.  Each stage's units
+// are split into 8 contiguous ranges of about equal cost, one per XCD.
+struct BatchTable {
+    int32_t n_items;
+    int32_t pad_;
+    int64_t fir_units, gemm_units, st_units;
+    int64_t fir_bounds[9], gemm_bounds[9], st_bounds[9];
+    BatchItem items[1];     // n_items entries follow
+};
+
+// Index of the item that owns unit u of a stage (0 FIR, 1 GEMM, 2 state):
+// the last item whose first unit is <= u.
+__device__ inline int batch_find(const BatchItem* items, int n, int64_t u, int stage) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t s = stage == 0 ? items[mid].fir_unit0 : (stage == 1 ? items[mid].gemm_unit0 : items[mid].st_unit0);
+        if (s <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// GEMM tile geometry shared with the batch planner.
+constexpr int kGemmBM = 128, kGemmBN = 128;
+
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int grid, hipStream_t s);
+hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_t s);
+hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s);
+
 }  // namespace tina

@@ -16,95 +16,17 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
-#include "tina_pfb.h"
+#include "runtime_types.h"
 
 using namespace tina;
 
-namespace {
-
 thread_local std::string g_err;
 
-tina_status fail(tina_status s, const std::string& msg) {
+tina_status tina_fail(tina_status s, const std::string& msg) {
     g_err = msg;
     return s;
 }
 
-#define HIP_TRY(call)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (call);                                                                    \
-        if (e_ != hipSuccess) return fail(TINA_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-// Makes `dev` current for the scope of a call and restores the caller's device.
-struct DeviceScope {
-    int prev = -1, dev;
-    hipError_t err = hipSuccess;
-    explicit DeviceScope(int d) : dev(d) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceScope() {
-        if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
-    }
-};
-
-constexpr int64_t kWorkspaceBytes = 512ll << 20;  // FP32 FIR output per piece
-
-bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
-}  // namespace
-
-struct tina_pfb_plan_s {
-    int device = 0;
-    int P = 0, M = 0, cf = 1, W = 0;  // W = floats per frame
-    int K = 0, N = 0;                 // GEMM inner and column dims
-    int64_t kout = 0;                 // output channels (or P for FIR-only)
-    int sample_type = 0, window = 0, precision = 0, output = 0;
-    double* h64 = nullptr;
-    float* h32 = nullptr;
-    void* B[2] = {nullptr, nullptr};
-    float* ws = nullptr;
-    float* amax = nullptr;
-    int64_t ch_frames = 0;
-    int64_t amax_parts_cap = 0;
-    // Stage timing (tina_pfb_profile_*): recorded event pairs per stage.
-    bool profiling = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fir, ev_dft;
-
-    hipEvent_t next_event() {
-        if (ev_used == ev_pool.size()) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            ev_pool.push_back(e);
-        }
-        return ev_pool[ev_used++];
-    }
-    void clear_events() {
-        ev_used = 0;
-        ev_fir.clear();
-        ev_dft.clear();
-    }
-
-    void release() {
-        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        ev_pool.clear();
-        clear_events();
-        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax})
-            if (p) (void)hipFree(p);
-        h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr;
-    }
-};
-
-struct tina_pfb_state_s {
-    tina_pfb_plan_s* plan = nullptr;
-    float* buf[2] = {nullptr, nullptr};
-    int cur = 0;
-    int64_t residue = 0;     // samples
-    int64_t cap_floats = 0;  // floats per buffer
-};
 
 extern "C" {
 

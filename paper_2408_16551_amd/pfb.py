@@ -30,6 +30,8 @@ EXPORTS = [
     "tina_pfb_state_create", "tina_pfb_state_destroy", "tina_pfb_state_reset", "tina_pfb_state_size",
     "tina_pfb_state_export", "tina_pfb_state_import",
     "tina_pfb_profile_enable", "tina_pfb_profile_read",
+    "tina_pfb_batch_create", "tina_pfb_batch_destroy", "tina_pfb_batch_execute", "tina_pfb_batch_tune",
+    "tina_pfb_batch_split_units",
 ]
 
 
@@ -37,6 +39,12 @@ class TinaError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class _Work(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("state", ctypes.c_void_p), ("d_in", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("d_out", ctypes.c_void_p),
+                ("out_capacity_frames", ctypes.c_int64), ("frames_written", ctypes.c_int64)]
 
 
 class _Desc(ctypes.Structure):
@@ -76,6 +84,12 @@ def load(path: str = LIB_PATH):
         "tina_pfb_state_import": ([vp, vp, i64], i32),
         "tina_pfb_profile_enable": ([vp, i32], i32),
         "tina_pfb_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), P64, ctypes.POINTER(ctypes.c_double), P64], i32),
+        "tina_pfb_batch_create": ([i32, i32, i32, i64, ctypes.POINTER(vp)], i32),
+        "tina_pfb_batch_destroy": ([vp], i32),
+        "tina_pfb_batch_split_units": ([vp, vp, i32, vp], i32),
+        "tina_pfb_batch_execute": ([vp, ctypes.POINTER(_Work), i32, vp], i32),
+        "tina_pfb_batch_tune": ([vp, ctypes.POINTER(_Work), i32, vp, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -229,3 +243,67 @@ class State:
         dt = np.complex64 if self.plan.complex_input else np.float32
         b = np.ascontiguousarray(buf, dtype=dt)
         check(load().tina_pfb_state_import(self.handle, b.ctypes.data_as(ctypes.c_void_p), b.size))
+
+
+class Batch:
+    """Batched execution: many (plan, input, output, state) chunks per call,
+    one persistent launch per stage."""
+
+    def __init__(self, precision: str = "fp32", max_items: int = 256, workspace_bytes: int = 1 << 30,
+                 device: int = 0):
+        h = ctypes.c_void_p()
+        check(load().tina_pfb_batch_create(int(device), PRECISION[precision], int(max_items), int(workspace_bytes),
+                                           ctypes.byref(h)))
+        self.handle = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tina_pfb_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _works(items):
+        arr = (_Work * max(1, len(items)))()
+        for i, it in enumerate(items):
+            plan, x, out = it[0], it[1], it[2]
+            state = it[3] if len(it) > 3 else None
+            w = arr[i]
+            w.plan = plan.handle.value
+            w.state = state.handle.value if state is not None else None
+            w.d_in = x.data_ptr() if x.numel() else None
+            w.n_samples = x.numel()
+            w.d_out = out.data_ptr() if out.numel() else None
+            w.out_capacity_frames = out.shape[0]
+        return arr
+
+    def execute(self, items, stream=None):
+        """items: list of (plan, x, out[, state]); returns frames written per item."""
+        arr = self._works(items)
+        check(load().tina_pfb_batch_execute(self.handle, arr, len(items), _stream_handle(stream)))
+        return [arr[i].frames_written for i in range(len(items))]
+
+    def tune(self, items, stream=None):
+        """Autotune launch shapes on this batch shape; returns (fir_tf_mult, gemm_blocks_per_cu)."""
+        arr = self._works(items)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(load().tina_pfb_batch_tune(self.handle, arr, len(items), _stream_handle(stream), ctypes.byref(a),
+                                         ctypes.byref(b)))
+        return a.value, b.value
+
+
+def split_units(units, cost):
+    """Cost-balanced split of a stage's units into 8 contiguous XCD ranges
+    (host-only helper of the batched launch); returns 9 bounds."""
+    u = np.ascontiguousarray(units, dtype=np.int64)
+    c = np.ascontiguousarray(cost, dtype=np.float64)
+    b = np.zeros(9, dtype=np.int64)
+    check(load().tina_pfb_batch_split_units(u.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+                                            len(u), b.ctypes.data_as(ctypes.c_void_p)))
+    return b

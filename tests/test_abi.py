@@ -81,3 +81,25 @@ def test_null_arguments_rejected(lib):
 
 def test_version_string(lib):
     assert b"gfx950" in lib.tina_version()
+
+
+@pytest.mark.parametrize("units,cost", [
+    ([4, 8, 0, 0, 1, 4, 32, 6], [512.0] * 8),
+    ([0, 0, 0], [1.0, 2.0, 3.0]),
+    ([], []),
+    ([1], [5.0]),
+    ([100, 3, 7000, 1], [4096.0, 512.0, 1024.0, 8192.0]),
+    ([5, 5, 5, 5, 5, 5, 5, 5, 5, 5], [1.0, 9.0] * 5),
+])
+def test_batch_split_covers_every_unit_once(lib, units, cost):
+    import numpy as np
+    from paper_2408_16551_amd import pfb
+    b = pfb.split_units(units, cost)
+    assert b[0] == 0 and b[8] == sum(units)
+    assert np.all(np.diff(b) >= 0)
+    # balance: no range exceeds an eighth of the cost by more than the largest unit
+    if sum(units):
+        per = np.repeat(np.asarray(cost, float), units)
+        csum = np.concatenate([[0.0], np.cumsum(per)])
+        shares = csum[b[1:]] - csum[b[:-1]]
+        assert shares.max() <= csum[-1] / 8 + max(cost) + 1e-9
