@@ -150,6 +150,144 @@ def cpu_baseline(w, target_s=12.0):
                       f"direct-sum DFT, {dt:.1f} s wall on {o.threads()} OpenMP threads"}
 
 
+def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
+    """The ragged batch: 64 complex64 streams, log-uniform lengths 2^18-2^22,
+    channels from {256, 512, 1024}, 16 taps, one persistent launch per stage,
+    autotuned launch shapes."""
+    from paper_2408_16551_amd import workloads
+    from paper_2408_16551_amd.pfb import Batch, Plan
+    specs, xs = workloads.ragged_batch()
+    total = int(sum(x.size for x in xs))
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    res = {"streams": len(specs), "samples": total,
+           "channels_mix": {str(P): sum(1 for s in specs if s.P == P) for P in sorted({s.P for s in specs})}}
+    for prec in precisions:
+        plans = {P: Plan(P, 16, "c64", "hann", prec, workspace_bytes=-1) for P in {s.P for s in specs}}
+        outs = [torch.empty((x.size // s.P, s.P), dtype=torch.complex64, device="cuda") for s, x in zip(specs, xs)]
+        items = [(plans[s.P], x, o) for s, x, o in zip(specs, xd, outs)]
+        b = Batch(prec, max_items=len(items), workspace_bytes=2 << 30)
+        tf, bpc = b.tune(items)
+        for _ in range(2):
+            b.execute(items)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            b.execute(items)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / steps
+        flops = sum(dft_flops_per_frame(s.P, True) * (x.size // s.P) for s, x in zip(specs, xs))
+        res[prec] = {"gsps": round(total / sec / 1e9, 3), "ms_per_batch": round(sec * 1e3, 3),
+                     "dft_useful_tflops_incl_fir": round(flops / sec / 1e12, 2),
+                     "tuned": {"fir_frames_per_thread_mult": tf, "gemm_blocks_per_cu": bpc}}
+        log(f"[bench] batched {prec}: {res[prec]}")
+        b.close()
+        del outs, items
+    return res
+
+
+def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005):
+    """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
+    1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
+    random stream, length log-uniform 2^16-2^22.  The rate is rho times the
+    capacity measured with a closed burst.  Latency = done - scheduled arrival,
+    including the host-to-device and device-to-host copies."""
+    import threading
+    from paper_2408_16551_amd import workloads
+    from paper_2408_16551_amd.pfb import Server
+    streams = workloads.serving_streams(seed)
+    sv = Server(precision, max_streams=len(streams), max_active=32, hbm_budget_bytes=budget_bytes,
+                frames_per_step=256, use_graph=True, max_channels=4096)
+    sids = [sv.stream(s.P, s.M, "c64") for s in streams]
+    g = np.random.Generator(np.random.PCG64(seed + 7))
+    max_len = 1 << 22
+    pool = torch.empty(max_len * 8, dtype=torch.complex64, pin_memory=True).numpy()
+    pool[:] = workloads.random_tone_stream(g, pool.size, 4)
+    n_out = 64   # output buffers in flight (frames * P <= residue + n < max_len + 4096)
+    out_pool = [torch.empty(max_len + 4096, dtype=torch.complex64, pin_memory=True).numpy() for _ in range(n_out)]
+    free_out = list(range(n_out))
+    lock = threading.Condition()
+    residues = [0] * len(streams)
+
+    def make(i, sid, n):
+        P = streams[sid].P
+        frames = (residues[sid] + n) // P
+        residues[sid] = (residues[sid] + n) % P
+        off = int(g.integers(0, pool.size - n + 1))
+        return pool[off: off + n], frames
+
+    def lens(k):
+        return np.floor(2.0 ** g.uniform(16.0, 22.0, size=k)).astype(np.int64)
+
+    # closed-loop capacity: a burst of 64 requests
+    burst = []
+    L = lens(64)
+    t0 = time.perf_counter()
+    for i, n in enumerate(L):
+        sid = i % len(streams)
+        x, frames = make(i, sid, int(n))
+        oi = free_out.pop()
+        out = out_pool[oi][: frames * streams[sid].P].reshape(frames, streams[sid].P)
+        burst.append((sv.submit(sids[sid], x, out), oi))
+    for rid, oi in burst:
+        sv.wait(rid)
+        free_out.append(oi)
+    cap = float(L.sum()) / (time.perf_counter() - t0)
+    mean_len = float(np.mean(lens(100000)))
+    lam = rho * cap / mean_len
+    # open loop
+    N = n_warm + n_meas
+    arrivals = np.cumsum(g.exponential(1.0 / lam, size=N))
+    sid_seq = g.integers(0, len(streams), size=N)
+    len_seq = lens(N)
+    lat, blocked = [None] * N, [0]
+    done_ids = []
+    base = sv.stats()["now_us"] * 1e-6 - time.perf_counter()   # server clock - host clock
+
+    def collector(q):
+        for i, rid, oi in iter(q.get, None):
+            r = sv.wait(rid)
+            lat[i] = (r["t_done_us"] * 1e-6 - (arrivals[i] + t_start + base)) * 1e3
+            with lock:
+                free_out.append(oi)
+                lock.notify_all()
+
+    import queue as _q
+    q = _q.Queue()
+    th = threading.Thread(target=collector, args=(q,), daemon=True)
+    th.start()
+    t_start = time.perf_counter()
+    samples_meas = 0
+    for i in range(N):
+        wait = arrivals[i] - (time.perf_counter() - t_start)
+        if wait > 0:
+            time.sleep(wait)
+        sid = int(sid_seq[i])
+        x, frames = make(i, sid, int(len_seq[i]))
+        with lock:
+            while not free_out:
+                blocked[0] += 1
+                lock.wait()
+            oi = free_out.pop()
+        out = out_pool[oi][: frames * streams[sid].P].reshape(frames, streams[sid].P)
+        q.put((i, sv.submit(sids[sid], x, out), oi))
+        if i >= n_warm:
+            samples_meas += int(len_seq[i])
+    q.put(None)
+    th.join()
+    t_total = time.perf_counter() - t_start - arrivals[n_warm - 1] if n_warm else time.perf_counter() - t_start
+    st = sv.stats()
+    sv.close()
+    m = np.array(lat[n_warm:], dtype=np.float64)
+    return {"precision": precision, "hbm_budget_bytes": budget_bytes, "rho": rho,
+            "capacity_gsps_closed_burst": round(cap / 1e9, 3), "rate_req_per_s": round(lam, 1),
+            "mean_request_samples": round(mean_len), "requests_measured": n_meas, "warmup_requests": n_warm,
+            "p50_ms": round(float(np.percentile(m, 50)), 3), "p99_ms": round(float(np.percentile(m, 99)), 3),
+            "mean_ms": round(float(m.mean()), 3), "gsps_served": round(samples_meas / t_total / 1e9, 3),
+            "admission_waits": st["admission_waits"], "steps": st["steps"],
+            "device_busy_frac": round(st["device_busy_ms"] / (st["now_us"] / 1e3), 3),
+            "submitter_blocked_on_output_buffers": blocked[0]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
+    ap.add_argument("--no-batched", action="store_true", help="skip the ragged batched workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -239,6 +379,14 @@ def main():
                               "hbm_frac": round(fir_bytes / (f2 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
         del fout, xd
         fplan.close()
+
+    if not args.no_batched:
+        log("[bench] batched ragged workload")
+        result["batched"] = batched_bench(torch)
+    if not args.no_serving:
+        log("[bench] serving workload")
+        result["serving"] = [serving_bench(torch, prec, bud) for prec in ("fp8", "bf16x3")
+                             for bud in (8 << 30, 256 << 20)]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")

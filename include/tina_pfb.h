@@ -105,6 +105,11 @@ typedef struct tina_pfb_desc {
     int32_t device;            /* HIP device ordinal */
     const double* custom_taps; /* host, P*M doubles, read during tina_pfb_plan when
                                   window == TINA_WINDOW_CUSTOM; otherwise NULL */
+    int64_t workspace_bytes;   /* FIR workspace of tina_pfb_execute: 0 = default (512 MiB),
+                                  < 0 = none (the plan is used only through batches or a
+                                  server, and tina_pfb_execute returns UNSUPPORTED).
+                                  Descriptors whose struct_size ends before this field
+                                  get the default. */
 } tina_pfb_desc;
 
 typedef struct tina_pfb_plan_s* tina_pfb_plan_t;
@@ -120,9 +125,10 @@ const char* tina_version(void);
  * Create a plan: designs the prototype window and the DFT operand (the
  * Fourier matrix of Sec. 4.1 in the operand form of the chosen precision) on
  * the device in FP64, then rounds them to the forms the kernels use.  The
- * plan owns all of its device memory, including a 512 MiB FP32 workspace
- * for the FIR output (execute runs inputs with more frames than it holds
- * as consecutive pieces), and synchronises once before returning.
+ * plan owns all of its device memory, including an FP32 workspace for the
+ * FIR output (desc->workspace_bytes, default 512 MiB; execute runs inputs
+ * with more frames than it holds as consecutive pieces), and synchronises
+ * once before returning.
  * Errors: INVALID_ARGUMENT (bad descriptor), UNSUPPORTED (P or M outside the
  * ranges above), OUT_OF_MEMORY, DEVICE.
  */

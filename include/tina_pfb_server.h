@@ -1,0 +1,139 @@
+/*
+ * tina_pfb_server.h -- continuous-batching channelizer server (C ABI).
+ *
+ * Serves filter-bank requests (TINA, arXiv 2408.16551, Sec. 5.2, Eq. (20))
+ * on many logical streams.  Each logical stream has its own channel count,
+ * taps, window and a device-resident filter state (the last (M-1)*P samples
+ * and the partial-frame residue), so consecutive requests of a stream are
+ * consecutive chunks of one signal: the concatenated outputs equal the
+ * filter bank of the concatenated inputs.
+ *
+ * A server thread runs steps back to back.  Requests queue in arrival order
+ * and are admitted while a slot is free and their device buffers (input and
+ * output) fit the HBM budget; a stream runs one request at a time, in order.
+ * Each step gives every admitted request whose input has reached the device
+ * up to `frames_per_step` frames of work and runs them together as one
+ * batched launch per stage (tina_pfb_batch.h), optionally replayed from a
+ * captured HIP graph, so requests that arrive while others run join at the
+ * next step and their work overlaps on the device.  Input copies to the
+ * device and output copies back run on a separate HIP stream.
+ *
+ * Same conventions as tina_pfb.h: tina_status results, tina_last_error(),
+ * validation before anything is queued.  All calls are thread-safe.
+ */
+#ifndef TINA_PFB_SERVER_H
+#define TINA_PFB_SERVER_H
+
+#include <stdint.h>
+
+#include "tina_pfb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tina_server_s* tina_server_t;
+
+typedef struct tina_server_config {
+    uint32_t struct_size;      /* sizeof(tina_server_config) */
+    int32_t device;            /* HIP device ordinal */
+    int32_t precision;         /* tina_precision of every stream's DFT */
+    int32_t max_streams;       /* logical streams, >= 1 */
+    int32_t max_active;        /* requests admitted at once (slots), >= 1 */
+    int32_t max_queued;        /* requests waiting for admission; submit returns BUSY beyond */
+    int64_t hbm_budget_bytes;  /* device arena for request input and output buffers */
+    int64_t frames_per_step;   /* frames of work per request per step, >= 1 */
+    int32_t use_graph;         /* nonzero: each step replays a captured HIP graph */
+    int32_t max_channels;      /* largest P any stream will use (sizes the step workspace) */
+} tina_server_config;
+
+/* Create a server and start its thread.  The server owns the arena
+ * (hbm_budget_bytes), a batch context and its step workspace
+ * (max_active * frames_per_step * 2 * max_channels floats), and two HIP
+ * streams.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
+tina_status tina_server_create(const tina_server_config* cfg, tina_server_t* out_server);
+
+/* Stop the thread after the admitted requests finish, fail the queued ones
+ * with TINA_ERR_CANCELLED, and release everything.  NULL is accepted. */
+tina_status tina_server_destroy(tina_server_t server);
+
+/* Register a logical stream with P channels (power of two, 16..max_channels),
+ * M taps (1..64), a sample type and a window (not CUSTOM).  Plans are shared
+ * between streams with the same parameters; each stream owns its state
+ * (2 * M * P samples of device memory, outside the arena).  Returns its id. */
+tina_status tina_server_stream_create(tina_server_t server, int32_t channels, int32_t taps, int32_t sample_type,
+                                      int32_t window, int32_t* stream_id);
+
+/* One request: the next n_samples samples of stream `stream_id`, read from
+ * host_in (host memory; pinned memory makes the copy asynchronous), the
+ * output rows written to host_out (host memory, room for
+ * out_capacity_frames rows of the stream's output, layout as
+ * tina_pfb_execute).  Both host buffers are lent to the server until the
+ * request is reported done. */
+typedef struct tina_request {
+    int32_t stream_id;
+    int32_t pad_;
+    const void* host_in;
+    int64_t n_samples;
+    void* host_out;
+    int64_t out_capacity_frames;
+} tina_request;
+
+typedef struct tina_result {
+    int32_t status;            /* TINA_OK, or the error that ended the request */
+    int32_t pad_;
+    int64_t frames;            /* output rows written to host_out */
+    double t_submit_us;        /* server clock (microseconds since server creation) */
+    double t_admit_us;         /* admitted: arena allocated, input copy queued */
+    double t_first_step_us;    /* first step containing this request was launched */
+    double t_done_us;          /* output copied back to host_out */
+    int32_t steps;             /* steps the request took part in */
+    int32_t pad2_;
+} tina_result;
+
+/* Queue a request.  Errors (nothing queued): INVALID_ARGUMENT (bad stream
+ * id, NULL buffers, output capacity below the frame count this request
+ * completes), TOO_LARGE (its buffers can never fit the budget), BUSY (the
+ * queue is full), CANCELLED (the server is stopping). */
+tina_status tina_pfb_submit(tina_server_t server, const tina_request* req, uint64_t* request_id);
+
+/* Result of a request: TINA_ERR_NOT_READY while it runs; otherwise TINA_OK
+ * with *result filled (the request is then forgotten; a later poll of the
+ * same id returns INVALID_ARGUMENT). */
+tina_status tina_pfb_poll(tina_server_t server, uint64_t request_id, tina_result* result);
+
+/* As tina_pfb_poll, but waits up to timeout_us microseconds (negative:
+ * forever); TINA_ERR_TIMEOUT when it runs out. */
+tina_status tina_pfb_wait(tina_server_t server, uint64_t request_id, int64_t timeout_us, tina_result* result);
+
+/* Cancel a request that has not been admitted yet (TINA_OK), or report
+ * NOT_READY if it is already running (it then completes normally). */
+tina_status tina_pfb_cancel(tina_server_t server, uint64_t request_id);
+
+typedef struct tina_server_stats {
+    int64_t steps;             /* steps launched */
+    int64_t samples;           /* input samples processed */
+    int64_t frames;            /* output frames produced */
+    int64_t completed;         /* requests completed */
+    int64_t admitted;          /* requests admitted */
+    int64_t admission_waits;   /* times the queue head waited for arena memory */
+    double device_busy_ms;     /* summed step durations (HIP events) */
+    double now_us;             /* server clock */
+    int64_t arena_in_use;      /* bytes currently allocated in the arena */
+    int64_t arena_high_water;  /* largest arena use so far */
+} tina_server_stats;
+
+tina_status tina_server_get_stats(tina_server_t server, tina_server_stats* stats);
+
+/* Host-only check of the server's arena allocator (first fit, 256-byte
+ * granules, coalescing on release), exposed for tests; no device work.
+ * ops[i] > 0 allocates ops[i] bytes: out[i] = offset, or -1 if it does not
+ * fit.  ops[i] <= 0 releases the allocation made by operation -ops[i]:
+ * out[i] = 1 if released, else 0.  *final_used = bytes allocated at the end. */
+tina_status tina_server_arena_simulate(int64_t capacity, const int64_t* ops, int32_t n, int64_t* out,
+                                       int64_t* final_used);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TINA_PFB_SERVER_H */

@@ -88,8 +88,13 @@ struct tina_pfb_batch_s {
     bool table_pending = false;
     Tune tune;
     bool have_tune = false;
+    // Captured step graphs (table upload + three persistent launches), keyed by
+    // the kernel variant: tap ring, exact taps, launch shape.
+    std::map<std::string, hipGraphExec_t> graphs;
 
     void release() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
         if (table_free) (void)hipEventDestroy(table_free);
         if (h_table) (void)hipHostFree(h_table);
         for (void* p : {(void*)ws, (void*)amax, (void*)d_table})
@@ -277,9 +282,22 @@ std::vector<GroupPlan> make_groups(tina_pfb_batch_s* b, tina_pfb_work* w, const 
     return gs;
 }
 
+tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
+                          bool always) {
+    const int grid_fir = b->cus * 4;
+    const int grid_gemm = b->cus * tune.gemm_blocks_per_cu;
+    if (always || b->h_table->fir_units > 0)
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), grid_fir, s));
+    if (always || b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, grid_gemm, s));
+    if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
+    return TINA_OK;
+}
+
 tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, const Tune& tune, bool dry,
-                      const std::vector<int64_t>& frames) {
-    for (const GroupPlan& g : make_groups(b, w, frames, n)) {
+                      const std::vector<int64_t>& frames, bool use_graph = false) {
+    const std::vector<GroupPlan> groups = make_groups(b, w, frames, n);
+    use_graph = use_graph && groups.size() == 1;
+    for (const GroupPlan& g : groups) {
         if (b->table_pending) {
             HIP_TRY(hipEventSynchronize(b->table_free));  // host copy of the table is free again
             b->table_pending = false;
@@ -287,16 +305,37 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
         int max_m = 1;
         bool all_exact = true;
         fill_table(b, w, frames, g, tune, dry, max_m, all_exact);
-        const size_t bytes = table_size(g.count);
-        HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, bytes, hipMemcpyHostToDevice, s));
+        if (use_graph) {
+            // Fixed topology: the full-size table upload and all three launches
+            // (a stage with no units returns at once), so one graph per kernel
+            // variant serves every step.
+            const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
+                                    std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_blocks_per_cu);
+            auto it = b->graphs.find(key);
+            if (it == b->graphs.end()) {
+                hipGraph_t graph = nullptr;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                hipError_t e = hipMemcpyAsync(b->d_table, b->h_table, b->table_bytes, hipMemcpyHostToDevice, s);
+                tina_status st = e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true) : TINA_ERR_DEVICE;
+                hipError_t e2 = hipStreamEndCapture(s, &graph);
+                if (e != hipSuccess || st != TINA_OK || e2 != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return fail(TINA_ERR_DEVICE, "batch: step graph capture failed");
+                }
+                hipGraphExec_t exec = nullptr;
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return fail(TINA_ERR_DEVICE, std::string("batch: graph instantiate: ") + hipGetErrorString(e));
+                it = b->graphs.emplace(key, exec).first;
+            }
+            HIP_TRY(hipGraphLaunch(it->second, s));
+        } else {
+            HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
+            tina_status st = launch_stages(b, s, tune, max_m, all_exact, false);
+            if (st != TINA_OK) return st;
+        }
         HIP_TRY(hipEventRecord(b->table_free, s));
         b->table_pending = true;
-        const int grid_fir = b->cus * 4;
-        const int grid_gemm = b->cus * tune.gemm_blocks_per_cu;
-        if (b->h_table->fir_units > 0)
-            HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), grid_fir, s));
-        if (b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, grid_gemm, s));
-        if (b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
         if (!dry) {
             for (int i = 0; i < g.count; ++i) {
                 tina_pfb_work& it = w[g.first + i];
@@ -330,6 +369,23 @@ std::string signature(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<i
 }
 
 }  // namespace
+
+// Used by the server: run one step's items, through the cached step graph
+// when use_graph is set.
+tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph) {
+    std::vector<int64_t> frames;
+    tina_status st = validate(b, w, n, frames);
+    if (st != TINA_OK) return st;
+    DeviceScope ds(b->device);
+    Tune tune;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune_cache.find(signature(b, w, frames, n));
+        if (it != g_tune_cache.end()) tune = it->second;
+    }
+    return run_batch(b, w, n, s, tune, false, frames, use_graph);
+}
 
 extern "C" {
 

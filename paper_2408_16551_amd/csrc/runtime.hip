@@ -9,6 +9,7 @@
 //   3. with a state: the new history and residue gathered into the state's
 //      other buffer (ping-pong, so the FIR of this call still reads the old one).
 // Inputs larger than the workspace run as consecutive frame pieces.
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -37,7 +38,9 @@ const char* tina_version(void) { return "tina_pfb 0.1 (gfx950)"; }
 tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     if (!d || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: NULL descriptor or output handle");
     *out = nullptr;
-    if (d->struct_size < sizeof(tina_pfb_desc)) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
+    if (d->struct_size < offsetof(tina_pfb_desc, workspace_bytes))
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
+    const int64_t ws_req = d->struct_size >= sizeof(tina_pfb_desc) ? d->workspace_bytes : 0;
     if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
     if (d->window < TINA_WINDOW_RECT || d->window > TINA_WINDOW_CUSTOM)
@@ -98,12 +101,13 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
             if (hipMalloc(&p->B[i], nbytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: DFT operand allocation");
         e = launch_dft_operand(p->B[0], p->B[1], p->P, p->cf == 2, form, nullptr);
         if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: DFT operand: ") + hipGetErrorString(e));
-        p->ch_frames = kWorkspaceBytes / ((int64_t)p->W * 4);
+        const int64_t ws_bytes = ws_req == 0 ? kWorkspaceBytes : ws_req;
+        p->ch_frames = ws_bytes > 0 ? ws_bytes / ((int64_t)p->W * 4) : 0;
         p->ch_frames = p->ch_frames >= 128 ? (p->ch_frames / 128) * 128 : p->ch_frames;
-        if (p->ch_frames < 1) p->ch_frames = 1;
-        if (hipMalloc(&p->ws, p->ch_frames * p->W * sizeof(float)) != hipSuccess)
+        if (ws_bytes > 0 && p->ch_frames < 1) p->ch_frames = 1;
+        if (p->ch_frames > 0 && hipMalloc(&p->ws, p->ch_frames * p->W * sizeof(float)) != hipSuccess)
             return bail(TINA_ERR_OUT_OF_MEMORY, "plan: workspace allocation");
-        if (form_scaled(form)) {
+        if (p->ch_frames > 0 && form_scaled(form)) {
             p->amax_parts_cap = p->W / 64 > 1 ? p->W / 64 : 1;
             if (hipMalloc(&p->amax, p->ch_frames * p->amax_parts_cap * sizeof(float)) != hipSuccess)
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: scale workspace allocation");
@@ -161,6 +165,8 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     if ((uintptr_t)d_out % obytes) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output misaligned");
     if (F > cap) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output capacity (" + std::to_string(cap) +
                                                          " frames) below frame count " + std::to_string(F));
+    if (p->output == TINA_OUT_PFB && p->ch_frames == 0)
+        return fail(TINA_ERR_UNSUPPORTED, "execute: plan was created without a workspace (batch/server use only)");
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute: hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;

@@ -86,3 +86,9 @@ struct tina_pfb_state_s {
     int64_t cap_floats = 0;  // floats per buffer
 };
 
+
+// Batched execution of one step's items (batch.hip), optionally through the
+// batch context's cached step graph.
+struct tina_pfb_batch_s;
+struct tina_pfb_work;
+tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph);

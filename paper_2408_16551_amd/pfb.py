@@ -32,6 +32,8 @@ EXPORTS = [
     "tina_pfb_profile_enable", "tina_pfb_profile_read",
     "tina_pfb_batch_create", "tina_pfb_batch_destroy", "tina_pfb_batch_execute", "tina_pfb_batch_tune",
     "tina_pfb_batch_split_units",
+    "tina_server_create", "tina_server_destroy", "tina_server_stream_create", "tina_pfb_submit", "tina_pfb_poll",
+    "tina_pfb_wait", "tina_pfb_cancel", "tina_server_get_stats", "tina_server_arena_simulate",
 ]
 
 
@@ -47,11 +49,38 @@ class _Work(ctypes.Structure):
                 ("out_capacity_frames", ctypes.c_int64), ("frames_written", ctypes.c_int64)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_streams", ctypes.c_int32), ("max_active", ctypes.c_int32), ("max_queued", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("frames_per_step", ctypes.c_int64),
+                ("use_graph", ctypes.c_int32), ("max_channels", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("stream_id", ctypes.c_int32), ("pad_", ctypes.c_int32), ("host_in", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("host_out", ctypes.c_void_p),
+                ("out_capacity_frames", ctypes.c_int64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad_", ctypes.c_int32), ("frames", ctypes.c_int64),
+                ("t_submit_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_first_step_us", ctypes.c_double), ("t_done_us", ctypes.c_double),
+                ("steps", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("samples", ctypes.c_int64), ("frames", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("admitted", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
+                ("device_busy_ms", ctypes.c_double), ("now_us", ctypes.c_double),
+                ("arena_in_use", ctypes.c_int64), ("arena_high_water", ctypes.c_int64)]
+
+
 class _Desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("channels", ctypes.c_int32), ("taps", ctypes.c_int32),
                 ("sample_type", ctypes.c_int32), ("window", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("output", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("custom_taps", ctypes.POINTER(ctypes.c_double))]
+                ("custom_taps", ctypes.POINTER(ctypes.c_double)), ("workspace_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -87,6 +116,15 @@ def load(path: str = LIB_PATH):
         "tina_pfb_batch_create": ([i32, i32, i32, i64, ctypes.POINTER(vp)], i32),
         "tina_pfb_batch_destroy": ([vp], i32),
         "tina_pfb_batch_split_units": ([vp, vp, i32, vp], i32),
+        "tina_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)], i32),
+        "tina_server_destroy": ([vp], i32),
+        "tina_server_stream_create": ([vp, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_int32)], i32),
+        "tina_pfb_submit": ([vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)], i32),
+        "tina_pfb_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_Result)], i32),
+        "tina_pfb_wait": ([vp, ctypes.c_uint64, i64, ctypes.POINTER(_Result)], i32),
+        "tina_pfb_cancel": ([vp, ctypes.c_uint64], i32),
+        "tina_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
+        "tina_server_arena_simulate": ([i64, vp, i32, vp, P64], i32),
         "tina_pfb_batch_execute": ([vp, ctypes.POINTER(_Work), i32, vp], i32),
         "tina_pfb_batch_tune": ([vp, ctypes.POINTER(_Work), i32, vp, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int32)], i32),
@@ -115,7 +153,8 @@ class Plan:
     the sample type, the DFT precision form and the output kind."""
 
     def __init__(self, channels: int, taps: int, sample_type: str = "r32", window: str = "hann",
-                 precision: str = "fp32", output: str = "pfb", device: int = 0, custom_taps=None):
+                 precision: str = "fp32", output: str = "pfb", device: int = 0, custom_taps=None,
+                 workspace_bytes: int = 0):
         lib = load()
         self.P, self.M = int(channels), int(taps)
         self.sample_type, self.precision, self.output = sample_type, precision, output
@@ -125,6 +164,7 @@ class Plan:
         d.channels, d.taps = self.P, self.M
         d.sample_type, d.window = SAMPLE[sample_type], WINDOW[window]
         d.precision, d.output, d.device = PRECISION[precision], OUTPUT[output], int(device)
+        d.workspace_bytes = int(workspace_bytes)
         self._custom = None
         if custom_taps is not None:
             self._custom = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -307,3 +347,104 @@ def split_units(units, cost):
     check(load().tina_pfb_batch_split_units(u.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
                                             len(u), b.ctypes.data_as(ctypes.c_void_p)))
     return b
+
+
+def arena_simulate(capacity: int, ops):
+    """Run the server's arena allocator on the host (no device): see
+    tina_server_arena_simulate.  Returns (per-op results, bytes in use)."""
+    o = np.ascontiguousarray(ops, dtype=np.int64)
+    out = np.zeros(len(o), dtype=np.int64)
+    used = ctypes.c_int64()
+    check(load().tina_server_arena_simulate(int(capacity), o.ctypes.data_as(ctypes.c_void_p), len(o),
+                                            out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(used)))
+    return out, used.value
+
+
+class Server:
+    """Continuous-batching channelizer server (one thread, one device)."""
+
+    def __init__(self, precision: str = "fp32", max_streams: int = 64, max_active: int = 32, max_queued: int = 4096,
+                 hbm_budget_bytes: int = 8 << 30, frames_per_step: int = 256, use_graph: bool = True,
+                 max_channels: int = 4096, device: int = 0):
+        c = _ServerConfig()
+        c.struct_size = ctypes.sizeof(_ServerConfig)
+        c.device, c.precision = int(device), PRECISION[precision]
+        c.max_streams, c.max_active, c.max_queued = int(max_streams), int(max_active), int(max_queued)
+        c.hbm_budget_bytes, c.frames_per_step = int(hbm_budget_bytes), int(frames_per_step)
+        c.use_graph, c.max_channels = int(bool(use_graph)), int(max_channels)
+        h = ctypes.c_void_p()
+        check(load().tina_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self.handle = h
+        self._streams = {}
+        self._lent = {}   # request id -> (input, output) kept alive until done
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tina_server_destroy(self.handle)
+            self.handle = None
+            self._lent.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream(self, channels: int, taps: int, sample_type: str = "c64", window: str = "hann") -> int:
+        sid = ctypes.c_int32()
+        check(load().tina_server_stream_create(self.handle, int(channels), int(taps), SAMPLE[sample_type],
+                                               WINDOW[window], ctypes.byref(sid)))
+        self._streams[sid.value] = (int(channels), sample_type)
+        return sid.value
+
+    def out_rows(self, sid: int) -> int:
+        P, st = self._streams[sid]
+        return P if st == "c64" else P // 2 + 1
+
+    def submit(self, sid: int, x: np.ndarray, out: np.ndarray) -> int:
+        """Queue x (host array, float32 or complex64) for stream sid; the output
+        rows go to out (host complex64 array, frames x channels).  Both arrays
+        are held until the request is collected."""
+        r = _Request()
+        r.stream_id = int(sid)
+        r.host_in = x.ctypes.data if x.size else None
+        r.n_samples = x.size
+        r.host_out = out.ctypes.data if out.size else None
+        r.out_capacity_frames = out.shape[0] if out.ndim == 2 else 0
+        rid = ctypes.c_uint64()
+        check(load().tina_pfb_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        self._lent[rid.value] = (x, out)
+        return rid.value
+
+    @staticmethod
+    def _res(r: _Result):
+        return {"status": r.status, "frames": r.frames, "t_submit_us": r.t_submit_us, "t_admit_us": r.t_admit_us,
+                "t_first_step_us": r.t_first_step_us, "t_done_us": r.t_done_us, "steps": r.steps}
+
+    def poll(self, rid: int):
+        r = _Result()
+        st = load().tina_pfb_poll(self.handle, ctypes.c_uint64(rid), ctypes.byref(r))
+        if st == 6:
+            return None
+        check(st)
+        self._lent.pop(rid, None)
+        return self._res(r)
+
+    def wait(self, rid: int, timeout_s: float = -1.0):
+        r = _Result()
+        us = -1 if timeout_s < 0 else int(timeout_s * 1e6)
+        check(load().tina_pfb_wait(self.handle, ctypes.c_uint64(rid), us, ctypes.byref(r)))
+        self._lent.pop(rid, None)
+        return self._res(r)
+
+    def cancel(self, rid: int) -> bool:
+        st = load().tina_pfb_cancel(self.handle, ctypes.c_uint64(rid))
+        if st == 6:
+            return False
+        check(st)
+        return True
+
+    def stats(self):
+        s = _ServerStats()
+        check(load().tina_server_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}

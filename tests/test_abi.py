@@ -103,3 +103,35 @@ def test_batch_split_covers_every_unit_once(lib, units, cost):
         csum = np.concatenate([[0.0], np.cumsum(per)])
         shares = csum[b[1:]] - csum[b[:-1]]
         assert shares.max() <= csum[-1] / 8 + max(cost) + 1e-9
+
+
+def test_arena_first_fit_and_coalescing(lib):
+    from paper_2408_16551_amd import pfb
+    # allocate 3 x 1000 (256-byte granules), free the middle, refit, overflow, free all
+    ops = [1000, 1000, 1000, -1, 500, 200, 5000, -0, -2, -4, -5, 4096]
+    out, used = pfb.arena_simulate(4096, ops)
+    assert list(out[:3]) == [0, 1024, 2048]
+    assert out[3] == 1                       # released
+    assert out[4] == 1024                    # first fit reuses the hole
+    assert out[5] == 1536                    # 200 -> 256 bytes, first fit in the rest of the hole
+    assert out[6] == -1                      # does not fit
+    assert list(out[7:11]) == [1, 1, 1, 1]
+    assert out[11] == 0 and used == 4096     # everything coalesced back into one block
+
+
+def test_server_config_validated_before_device(lib):
+    from paper_2408_16551_amd import pfb
+    c = pfb._ServerConfig()
+    c.struct_size = ctypes.sizeof(pfb._ServerConfig)
+    c.device, c.precision, c.max_streams, c.max_active, c.max_queued = 0, 0, 4, 2, 8
+    c.hbm_budget_bytes, c.frames_per_step, c.use_graph, c.max_channels = 1 << 20, 64, 1, 1000
+    h = ctypes.c_void_p()
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1   # max_channels not a power of two
+    c.max_channels, c.frames_per_step = 1024, 0
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    c.frames_per_step, c.precision = 64, 17
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    assert not h.value
+    r = pfb._Request()
+    rid = ctypes.c_uint64()
+    assert lib.tina_pfb_submit(None, ctypes.byref(r), ctypes.byref(rid)) == 1

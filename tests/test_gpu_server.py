@@ -1,0 +1,157 @@
+"""Continuous-batching server: a stream's requests are consecutive chunks of
+one signal, so the concatenated outputs must equal one filter-bank pass over
+the concatenated input (bit for bit: same kernels, same arithmetic per output
+element), whether the stream runs alone or mixed with others, with or without
+graph replay, and under a budget that forces admission waits."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rand(N, cplx, g):
+    x = g.standard_normal(N)
+    if cplx:
+        return (x + 1j * g.standard_normal(N)).astype(np.complex64)
+    return x.astype(np.float32)
+
+
+# (P, M, cplx) per logical stream
+STREAMS = [(64, 8, True), (256, 16, True), (512, 11, True), (256, 16, False), (1024, 9, True)]
+
+
+def _workload(seed, n_req=24, streams=STREAMS):
+    g = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for _ in range(n_req):
+        s = int(g.integers(len(streams)))
+        P = streams[s][0]
+        n = int(g.choice([0, P // 3, P * int(g.integers(1, 40)) + int(g.integers(P)), P * 300 + 7]))
+        reqs.append((s, _rand(n, streams[s][2], g)))
+    return reqs
+
+
+def _serve(reqs, precision="fp32", use_graph=True, budget=1 << 30, max_active=8, fps=64, streams=STREAMS,
+           only=None):
+    from paper_2408_16551_amd.pfb import Server
+    sv = Server(precision, max_streams=len(streams), max_active=max_active, hbm_budget_bytes=budget,
+                frames_per_step=fps, use_graph=use_graph, max_channels=1024)
+    sids = [sv.stream(P, M, "c64" if c else "r32") for P, M, c in streams]
+    res = [0] * len(streams)
+    pending = []
+    for s, x in reqs:
+        if only is not None and s != only:
+            continue
+        P = streams[s][0]
+        frames = (res[s] + x.size) // P
+        res[s] = (res[s] + x.size) % P
+        out = np.full((frames, sv.out_rows(sids[s])), np.nan, dtype=np.complex64)
+        pending.append((s, sv.submit(sids[s], x, out), out))
+    outs = [[] for _ in streams]
+    results = []
+    for s, rid, out in pending:
+        r = sv.wait(rid, timeout_s=60)
+        assert r["status"] == 0
+        assert r["frames"] == out.shape[0]
+        outs[s].append(out)
+        results.append(r)
+    stats = sv.stats()
+    sv.close()
+    return [np.concatenate(o) if o else None for o in outs], results, stats
+
+
+def _one_shot(reqs, precision, streams=STREAMS):
+    from paper_2408_16551_amd.pfb import Plan
+    ref = []
+    for s, (P, M, c) in enumerate(streams):
+        xs = [x for t, x in reqs if t == s]
+        if not xs:
+            ref.append(None)
+            continue
+        x = np.concatenate(xs)
+        plan = Plan(P, M, "c64" if c else "r32", "hann", precision)
+        X = plan(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        ref.append(X.cpu().numpy())
+    return ref
+
+
+@pytest.mark.parametrize("precision,use_graph", [("fp32", True), ("fp32", False), ("bf16x3", True), ("fp8", True)])
+def test_server_streams_equal_one_shot_bitwise(precision, use_graph):
+    reqs = _workload(seed=1)
+    got, results, stats = _serve(reqs, precision, use_graph)
+    ref = _one_shot(reqs, precision)
+    for g, r in zip(got, ref):
+        if r is None:
+            continue
+        assert g.shape == r.shape
+        assert np.array_equal(g, r)
+    assert stats["completed"] == len(reqs)
+    assert stats["steps"] >= 1
+    for r in results:
+        assert r["t_submit_us"] <= r["t_admit_us"] <= r["t_done_us"]
+
+
+def test_server_alone_equals_in_mix():
+    reqs = _workload(seed=2)
+    mixed, _, _ = _serve(reqs, "bf16x3")
+    for s in range(len(STREAMS)):
+        alone, _, _ = _serve(reqs, "bf16x3", only=s)
+        if mixed[s] is None:
+            continue
+        assert np.array_equal(alone[s], mixed[s])
+
+
+def test_server_small_budget_forces_admission_waits():
+    # Every request needs about the same arena space; the budget holds one
+    # request at a time, so the others wait for memory, not for slots.
+    g = np.random.Generator(np.random.PCG64(3))
+    reqs = [(s, _rand(STREAMS[s][0] * 200 + 11, STREAMS[s][2], g)) for _ in range(3) for s in range(len(STREAMS))]
+    need = max(x.nbytes + (x.size // STREAMS[s][0] + 1) * STREAMS[s][0] * 8 for s, x in reqs) + 1024
+    got, _, stats = _serve(reqs, "fp32", budget=int(need * 1.5), max_active=8)
+    ref = _one_shot(reqs, "fp32")
+    for g_, r in zip(got, ref):
+        if r is not None:
+            assert np.array_equal(g_, r)
+    assert stats["admission_waits"] > 0
+    assert stats["arena_high_water"] <= int(need * 1.5)
+    assert stats["completed"] == len(reqs)
+
+
+def test_server_fp32_matches_oracle(oracle):
+    from oracle import Stream
+    streams = [(256, 16, True), (512, 8, False)]
+    reqs = _workload(seed=4, n_req=10, streams=streams)
+    got, _, _ = _serve(reqs, "fp32", streams=streams)
+    for s, (P, M, c) in enumerate(streams):
+        if got[s] is None:
+            continue
+        o = Stream(oracle, P, M, oracle.window(P, M, "hann"), c)
+        ref = np.concatenate([o.push(x) for t, x in reqs if t == s])
+        err = np.linalg.norm(got[s].astype(np.complex128) - ref) / np.linalg.norm(ref)
+        assert err < 1e-5
+
+
+def test_server_rejects_too_large_and_cancels():
+    from paper_2408_16551_amd.pfb import Server, TinaError
+    sv = Server("fp32", max_streams=2, max_active=1, hbm_budget_bytes=1 << 20, frames_per_step=16, max_channels=256)
+    sid = sv.stream(256, 8, "c64")
+    big = np.zeros(1 << 20, dtype=np.complex64)
+    with pytest.raises(TinaError) as e:
+        sv.submit(sid, big, np.zeros((4096, 256), np.complex64))
+    assert e.value.status == 7
+    x = np.ones(256 * 10, dtype=np.complex64)
+    with pytest.raises(TinaError) as e:
+        sv.submit(sid, x, np.zeros((3, 256), np.complex64))   # capacity below 10 frames
+    assert e.value.status == 1
+    ids = [sv.submit(sid, x, np.zeros((10, 256), np.complex64)) for _ in range(3)]
+    cancelled = sv.cancel(ids[-1])
+    for rid in ids[:-1]:
+        assert sv.wait(rid, timeout_s=60)["status"] == 0
+    if cancelled:
+        assert sv.wait(ids[-1], timeout_s=60)["status"] == 9
+    else:
+        assert sv.wait(ids[-1], timeout_s=60)["status"] == 0
+    sv.close()
