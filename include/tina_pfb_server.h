@@ -16,7 +16,8 @@
  * batched launch per stage (tina_pfb_batch.h), optionally replayed from a
  * captured HIP graph, so requests that arrive while others run join at the
  * next step and their work overlaps on the device.  Input copies to the
- * device and output copies back run on a separate HIP stream.
+ * device and output copies back run on two more HIP streams, so both
+ * directions of the host link are used at once, beside the compute.
  *
  * Same conventions as tina_pfb.h: tina_status results, tina_last_error(),
  * validation before anything is queued.  All calls are thread-safe.
@@ -49,8 +50,9 @@ typedef struct tina_server_config {
 
 /* Create a server and start its thread.  The server owns the arena
  * (hbm_budget_bytes), a batch context and its step workspace
- * (max_active * frames_per_step * 2 * max_channels floats), and two HIP
- * streams.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
+ * (max_active * frames_per_step * 2 * max_channels floats), and three HIP
+ * streams (compute, host-to-device copies, device-to-host copies), all at the
+ * default priority.  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE. */
 tina_status tina_server_create(const tina_server_config* cfg, tina_server_t* out_server);
 
 /* Stop the thread after the admitted requests finish, fail the queued ones

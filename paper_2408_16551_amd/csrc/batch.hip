@@ -91,6 +91,7 @@ struct tina_pfb_batch_s {
     // Captured step graphs (table upload + three persistent launches), keyed by
     // the kernel variant: tap ring, exact taps, launch shape.
     std::map<std::string, hipGraphExec_t> graphs;
+    int64_t graph_gemm_grid = 0;  // fixed GEMM grid of captured steps (0: no graphs)
 
     void release() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -282,13 +283,22 @@ std::vector<GroupPlan> make_groups(tina_pfb_batch_s* b, tina_pfb_work* w, const 
     return gs;
 }
 
+// Blocks of the batched GEMM launch: 8 x the largest XCD range (one block per
+// tile), or the fixed bound of a captured step graph.
+int64_t gemm_grid(const BatchTable* t) {
+    int64_t mx = 0;
+    for (int x = 0; x < 8; ++x) mx = std::max(mx, t->gemm_bounds[x + 1] - t->gemm_bounds[x]);
+    return 8 * std::max<int64_t>(mx, 1);
+}
+
 tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
-                          bool always) {
+                          bool always, int64_t fixed_gemm_grid = 0) {
+    (void)tune;
     const int grid_fir = b->cus * 4;
-    const int grid_gemm = b->cus * tune.gemm_blocks_per_cu;
+    const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     if (always || b->h_table->fir_units > 0)
         HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), grid_fir, s));
-    if (always || b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, grid_gemm, s));
+    if (always || b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }
@@ -305,7 +315,8 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
         int max_m = 1;
         bool all_exact = true;
         fill_table(b, w, frames, g, tune, dry, max_m, all_exact);
-        if (use_graph) {
+        const bool graph_ok = use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid;
+        if (graph_ok) {
             // Fixed topology: the full-size table upload and all three launches
             // (a stage with no units returns at once), so one graph per kernel
             // variant serves every step.
@@ -316,7 +327,8 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
                 hipGraph_t graph = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipMemcpyAsync(b->d_table, b->h_table, b->table_bytes, hipMemcpyHostToDevice, s);
-                tina_status st = e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true) : TINA_ERR_DEVICE;
+                tina_status st =
+                    e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid) : TINA_ERR_DEVICE;
                 hipError_t e2 = hipStreamEndCapture(s, &graph);
                 if (e != hipSuccess || st != TINA_OK || e2 != hipSuccess) {
                     if (graph) (void)hipGraphDestroy(graph);
@@ -369,6 +381,13 @@ std::string signature(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<i
 }
 
 }  // namespace
+
+// Used by the server: the largest GEMM tile count of one of its steps, which
+// fixes the grid of the captured step graphs (the cost-balanced split may give
+// one XCD up to all of them).
+void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
+    b->graph_gemm_grid = 8 * std::max<int64_t>(max_gemm_tiles, 1);
+}
 
 // Used by the server: run one step's items, through the cached step graph
 // when use_graph is set.
@@ -477,7 +496,7 @@ tina_status tina_pfb_batch_tune(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n,
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int mults[] = {1, 2, 4};
-    const int bpcs[] = {1, 2};
+    const int bpcs[] = {1};  // the GEMM runs one block per tile; only the FIR shape is tuned
     Tune best;
     float best_ms = 1e30f;
     for (int m : mults)

@@ -16,6 +16,8 @@
 // instruction never has to be known.
 #include "internal.h"
 
+#include <stdlib.h>
+
 namespace tina {
 namespace {
 
@@ -58,43 +60,70 @@ __device__ inline uint32_t f16_pair(float a, float b) {
 __device__ inline float bf16_round(float a) { return (float)(__bf16)a; }
 __device__ inline float f16_round(float a) { return (float)(_Float16)a; }
 
-template <int FORM>
-__device__ inline void mfma_step(const uint4 (&a)[2][2], const uint4 (&b)[2][2], f32x16& acc, f32x16& acc2) {
+// The MFMAs of one K slab for the wave's 2 x 2 blocks.  Products are issued
+// term-major (every block's hi*hi, then every block's hi*lo, ...), so MFMAs
+// that accumulate into the same registers are four instructions apart.
+// af[bm][piece][read], bf[bn][piece][read]: the lane's 16-byte K slices.
+template <int FORM, int NP, int RD>
+__device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[2][NP][RD],
+                                          f32x16 (&acc)[2][2], f32x16 (&acc2)[2][2]) {
     if constexpr (FORM == FORM_FP32) {
-        const f32x4 av = __builtin_bit_cast(f32x4, a[0][0]);
-        const f32x4 bv = __builtin_bit_cast(f32x4, b[0][0]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bv[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bv[3], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    const f32x4 av = __builtin_bit_cast(f32x4, af[bm][0][0]);
+                    const f32x4 bv = __builtin_bit_cast(f32x4, bf[bn][0][0]);
+                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[bm][bn], 0, 0, 0);
+                }
     } else if constexpr (FORM == FORM_BF16 || FORM == FORM_BF16X3) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, a[0][0]);
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, b[0][0]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-        if constexpr (FORM == FORM_BF16X3) {
-            const bf16x8 al = __builtin_bit_cast(bf16x8, a[1][0]);
-            const bf16x8 bl = __builtin_bit_cast(bf16x8, b[1][0]);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc2, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc2, 0, 0, 0);
-        }
+        // BF16X3: hi*hi, hi*lo and lo*hi all accumulate into acc (the small
+        // terms are added in FP32, at FP32 accumulation accuracy).
+        constexpr int NT = FORM == FORM_BF16X3 ? 3 : 1;
+#pragma unroll
+        for (int term = 0; term < NT; ++term)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, af[bm][pa < NP ? pa : 0][0]);
+                    const bf16x8 b = __builtin_bit_cast(bf16x8, bf[bn][pb < NP ? pb : 0][0]);
+                    acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[bm][bn], 0, 0, 0);
+                }
     } else if constexpr (FORM == FORM_FP16 || FORM == FORM_FP16X3) {
-        const f16x8 ah = __builtin_bit_cast(f16x8, a[0][0]);
-        const f16x8 bh = __builtin_bit_cast(f16x8, b[0][0]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
-        if constexpr (FORM == FORM_FP16X3) {
-            const f16x8 al = __builtin_bit_cast(f16x8, a[1][0]);
-            const f16x8 bl = __builtin_bit_cast(f16x8, b[1][0]);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc2, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc2, 0, 0, 0);
-        }
+        // FP16X3: the two cross terms carry the lo pieces' 2^11 and go to acc2.
+        constexpr int NT = FORM == FORM_FP16X3 ? 3 : 1;
+#pragma unroll
+        for (int term = 0; term < NT; ++term)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
+                    const f16x8 a = __builtin_bit_cast(f16x8, af[bm][pa < NP ? pa : 0][0]);
+                    const f16x8 b = __builtin_bit_cast(f16x8, bf[bn][pb < NP ? pb : 0][0]);
+                    if (term == 0) acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[bm][bn], 0, 0, 0);
+                    else acc2[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc2[bm][bn], 0, 0, 0);
+                }
     } else {
-        i32x8 av, bv;
-        av[0] = a[0][0].x; av[1] = a[0][0].y; av[2] = a[0][0].z; av[3] = a[0][0].w;
-        av[4] = a[0][1].x; av[5] = a[0][1].y; av[6] = a[0][1].z; av[7] = a[0][1].w;
-        bv[0] = b[0][0].x; bv[1] = b[0][0].y; bv[2] = b[0][0].z; bv[3] = b[0][0].w;
-        bv[4] = b[0][1].x; bv[5] = b[0][1].y; bv[6] = b[0][1].z; bv[7] = b[0][1].w;
-        // Formats 0/0 = FP8 E4M3 for both operands; block scales 2^0 (E8M0 127).
-        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < 2; ++bn) {
+                i32x8 av, bv;
+                const uint4 a0 = af[bm][0][0], a1 = af[bm][0][RD - 1];
+                const uint4 b0 = bf[bn][0][0], b1 = bf[bn][0][RD - 1];
+                av[0] = a0.x; av[1] = a0.y; av[2] = a0.z; av[3] = a0.w;
+                av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
+                bv[0] = b0.x; bv[1] = b0.y; bv[2] = b0.z; bv[3] = b0.w;
+                bv[4] = b1.x; bv[5] = b1.y; bv[6] = b1.z; bv[7] = b1.w;
+                // Formats 0/0 = FP8 E4M3 for both operands; block scales 2^0 (E8M0 127).
+                acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[bm][bn], 0, 0, 0, 0x7f7f7f7f,
+                                                                              0, 0x7f7f7f7f);
+            }
     }
 }
 
@@ -236,7 +265,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         if (t + 1 < nk) load_tile((t + 1) * BK);
 #pragma unroll
         for (int s = 0; s < NSLAB; ++s) {
-            uint4 af[2][NP][2], bf[2][NP][2];
+            uint4 af[2][NP][RD], bf[2][NP][RD];
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -255,20 +284,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                         const int row = wn * 64 + bn * 32 + lr;
                         bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + s * SLAB + q * 32 + lh * 16);
                     }
-#pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
-                    uint4 a2[2][2], b2[2][2];
-#pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            a2[p][q] = af[bm][p < NP ? p : 0][q < RD ? q : 0];
-                            b2[p][q] = bf[bn][p < NP ? p : 0][q < RD ? q : 0];
-                        }
-                    mfma_step<FORM>(a2, b2, acc[bm][bn], acc2[bm][bn]);
-                }
+            mfma_slab<FORM, NP, RD>(af, bf, acc, acc2);
         }
         __syncthreads();
         if (t + 1 < nk) {
@@ -293,7 +309,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 const int64_t row = m0 + rloc;
                 if (row >= g.F) continue;
                 float val = acc[bm][bn][v];
-                if constexpr (NP == 2) val += acc2[bm][bn][v] * corr;
+                if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
                 if constexpr (ft::SCALED) val *= s_sc[rloc];
                 float* o = g.out + row * g.ldo;
                 o[oc] = val;
@@ -311,21 +327,23 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     gemm_tile<FORM>(g, m0, n0, sm);
 }
 
-// Persistent batched GEMM: each block walks its XCD's contiguous range of
-// tiles over all items (see BatchTable).
+// Batched GEMM, one block per tile of any item: block b serves tile
+// i = b / 8 of XCD x = b % 8's contiguous, cost-balanced range of tiles (see
+// BatchTable); blocks past the end of their range return at once.  (A
+// persistent loop over tiles keeps per-tile state live across iterations and
+// halves the occupancy, so each block does one tile.)
 template <int FORM>
 __global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __restrict__ t) {
     __shared__ __attribute__((aligned(16))) GemmSmem<FORM> sm;
-    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
-    const int64_t end = t->gemm_bounds[x + 1];
-    for (int64_t u = t->gemm_bounds[x] + i; u < end; u += nbx) {
-        const int it = batch_find(t->items, t->n_items, u, /*stage=*/1);
-        const GemmArgs& g = t->items[it].gemm;
-        const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
-        int64_t m0, n0;
-        grouped_tile(u - t->items[it].gemm_unit0, nm, nn, m0, n0);
-        gemm_tile<FORM>(g, m0, n0, sm);
-    }
+    const int x = blockIdx.x & 7;
+    const int64_t u = t->gemm_bounds[x] + (blockIdx.x >> 3);
+    if (u >= t->gemm_bounds[x + 1]) return;
+    const int it = batch_find(t->items, t->n_items, u, /*stage=*/1);
+    const GemmArgs& g = t->items[it].gemm;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(u - t->items[it].gemm_unit0, nm, nn, m0, n0);
+    gemm_tile<FORM>(g, m0, n0, sm);
 }
 
 template <int FORM>

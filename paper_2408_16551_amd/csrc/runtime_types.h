@@ -92,3 +92,5 @@ struct tina_pfb_state_s {
 struct tina_pfb_batch_s;
 struct tina_pfb_work;
 tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph);
+// Bound on the GEMM tiles of one step (fixes the grid of captured steps).
+void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles);

@@ -5,12 +5,13 @@
 //              request's device buffers fit the arena; a stream runs one
 //              request at a time (its state orders the chunks);
 //   copy in -- each admitted request's input goes to its arena buffer on the
-//              copy stream;
+//              host-to-device stream;
 //   step    -- every admitted request whose input is on the device gets up
 //              to frames_per_step frames; all of them run as one batched
 //              launch per stage (batch.hip), optionally a graph replay;
-//   copy out-- finished requests' output rows go back on the copy stream,
-//              then their arena buffers are freed and waiters are woken.
+//   copy out-- finished requests' output rows go back on the device-to-host
+//              stream (the two directions overlap on the link), then their
+//              arena buffers are freed and waiters are woken.
 // Requests that arrive while a step runs are admitted before the next one.
 #include <stddef.h>
 
@@ -138,7 +139,7 @@ struct tina_server_s {
     Arena arena;
     uint8_t* arena_base = nullptr;
     tina_pfb_batch_s* batch = nullptr;
-    hipStream_t s_comp = nullptr, s_copy = nullptr;
+    hipStream_t s_comp = nullptr, s_h2d = nullptr, s_d2h = nullptr;  // copies in and out on their own streams
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     std::chrono::steady_clock::time_point t0;
     tina_server_stats stats{};
@@ -213,8 +214,8 @@ void tina_server_s::loop() {
         for (Req* q : admitted) {  // input copies, outside the lock
             if (q->in_bytes > 0 && q->r.n_samples > 0)
                 (void)hipMemcpyAsync(arena_base + q->off_in, q->r.host_in, q->r.n_samples * q->sample_bytes,
-                                     hipMemcpyHostToDevice, s_copy);
-            (void)hipEventRecord(q->ev_in, s_copy);
+                                     hipMemcpyHostToDevice, s_h2d);
+            (void)hipEventRecord(q->ev_in, s_h2d);
         }
 
         // Build the step: every active request whose input is on the device.
@@ -282,8 +283,8 @@ void tina_server_s::loop() {
                 if (!empty && (q->samples_done < q->r.n_samples || !q->in_ready)) { ++it; continue; }
                 if (q->frames_done > 0)
                     (void)hipMemcpyAsync(q->r.host_out, arena_base + q->off_out, q->frames_done * q->row_bytes,
-                                         hipMemcpyDeviceToHost, s_copy);
-                (void)hipEventRecord(q->ev_out, s_copy);
+                                         hipMemcpyDeviceToHost, s_d2h);
+                (void)hipEventRecord(q->ev_out, s_d2h);
                 q->phase = DRAINING;
                 streams[q->r.stream_id].busy = false;
                 draining.push_back(q);
@@ -326,7 +327,7 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     auto bail = [&](tina_status st, const std::string& m) {
         if (sv->batch) tina_pfb_batch_destroy(sv->batch);
         if (sv->arena_base) (void)hipFree(sv->arena_base);
-        for (hipStream_t s : {sv->s_comp, sv->s_copy})
+        for (hipStream_t s : {sv->s_comp, sv->s_h2d, sv->s_d2h})
             if (s) (void)hipStreamDestroy(s);
         for (hipEvent_t e : {sv->ev_a, sv->ev_b})
             if (e) (void)hipEventDestroy(e);
@@ -338,8 +339,13 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     const int64_t ws = (int64_t)c->max_active * c->frames_per_step * 2 * c->max_channels * 4;
     tina_status st = tina_pfb_batch_create(c->device, c->precision, c->max_active, std::max<int64_t>(ws, 1 << 20), &sv->batch);
     if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
+    // Largest GEMM tile count of a step: every slot with frames_per_step
+    // frames of the widest stream (128 x 128 tiles, N = 2 * max_channels).
+    batch_set_graph_bound(sv->batch, (int64_t)c->max_active * ((c->frames_per_step + kGemmBM - 1) / kGemmBM) *
+                                         ((2 * (int64_t)c->max_channels + kGemmBN - 1) / kGemmBN));
     if (hipStreamCreateWithFlags(&sv->s_comp, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&sv->s_copy, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->s_h2d, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->s_d2h, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&sv->ev_a) != hipSuccess || hipEventCreate(&sv->ev_b) != hipSuccess)
         return bail(TINA_ERR_DEVICE, "server_create: streams/events");
     sv->th = std::thread([sv] { sv->loop(); });
@@ -369,7 +375,8 @@ tina_status tina_server_destroy(tina_server_t sv) {
     tina_pfb_batch_destroy(sv->batch);
     (void)hipFree(sv->arena_base);
     (void)hipStreamDestroy(sv->s_comp);
-    (void)hipStreamDestroy(sv->s_copy);
+    (void)hipStreamDestroy(sv->s_h2d);
+    (void)hipStreamDestroy(sv->s_d2h);
     (void)hipEventDestroy(sv->ev_a);
     (void)hipEventDestroy(sv->ev_b);
     delete sv;
