@@ -106,13 +106,14 @@ def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
     fr = sampled_frames(F, w.M, n_frames_err, seed=7)
     ref = oracle_obj.pfb(w.x, w.P, w.M, oracle_obj.window(w.P, w.M, w.window), frames=fr)
     res = {}
-    for form in forms:
-        plan = Plan(w.P, w.M, "c64" if w.complex_input else "r32", w.window, form, "pfb")
+    for entry in forms:
+        form, dft = (entry.split("/") + ["dense"])[:2]
+        plan = Plan(w.P, w.M, "c64" if w.complex_input else "r32", w.window, form, "pfb", dft=dft)
         out = plan.alloc_out(F)
         sec, fir_ms, dft_ms = timed_steps(plan, xd, out, steps, warmup, torch)
         got = out[torch.from_numpy(fr).cuda()].cpu().numpy()
         flops = dft_flops_per_frame(w.P, w.complex_input) * F
-        res[form] = {
+        res[entry] = {
             "gsps": round(N / sec / 1e9, 3),
             "ms_per_step": round(sec * 1e3, 4),
             "rel_l2_vs_fp64_oracle": float(f"{rel_l2(got, ref):.3e}"),
@@ -120,7 +121,15 @@ def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
             "dft_useful_tflops": round(flops / (dft_ms * 1e-3) / 1e12, 2),
             "dft_mfma_frac": round(flops * MFMA_FLOP_MULT[form] / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS[form], 4),
         }
-        log(f"[bench] {w.name} {form}: {res[form]}")
+        if dft == "factored":   # the dense-DFT flop figures do not apply
+            P1 = 1 << ((int(np.log2(w.P)) + 1) // 2)
+            f_fact = 8.0 * w.P * (P1 + w.P // P1) * F
+            res[entry]["dft_useful_tflops"] = round(f_fact / (dft_ms * 1e-3) / 1e12, 2)
+            res[entry]["dft_mfma_frac"] = round(f_fact / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4)
+            res[entry]["dft_bytes_gbs"] = round((4.0 * F * w.P * (2 if w.complex_input else 1)
+                                                 + 8.0 * F * (w.P if w.complex_input else w.P // 2 + 1))
+                                                / (dft_ms * 1e-3) / 1e9, 1)
+        log(f"[bench] {w.name} {entry}: {res[entry]}")
         plan.close()
         del out
     return res
@@ -148,6 +157,47 @@ def cpu_baseline(w, target_s=12.0):
     return {"value": round(n * w.P / dt / 1e9, 6), "unit": "GSamples/s", "cores": o.threads(), "kind": "oracle",
             "sample": f"first {n} of {F} frames ({n * w.P} input samples) of {w.name}, FP64 direct FIR + "
                       f"direct-sum DFT, {dt:.1f} s wall on {o.threads()} OpenMP threads"}
+
+
+def ops_bench(torch, steps=10):
+    """The standalone building blocks: unfold (GB/s of output written, the
+    bound) and the direct FIR with arbitrary taps (GSamples/s)."""
+    from paper_2408_16551_amd.pfb import Fir, unfold
+    res = {}
+    n = 1 << 26
+    x = torch.randn(n, device="cuda")
+    for width, stride in ((16, 16), (64, 16)):
+        rows = (n - width) // stride + 1
+        out = torch.empty((rows, width), device="cuda")
+        for _ in range(2):
+            unfold(x, width, stride, out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            unfold(x, width, stride, out=out)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / steps
+        by = 4.0 * rows * width + 4.0 * n
+        res[f"unfold_w{width}_s{stride}"] = {"ms": round(sec * 1e3, 4), "gbs": round(by / sec / 1e9, 1),
+                                             "hbm_frac": round(by / sec / 1e9 / PEAK_HBM_GBS, 4)}
+        del out
+    g = np.random.Generator(np.random.PCG64(3))
+    for K in (64, 1024):
+        f = Fir(g.standard_normal(K), "r32")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            f(x, out=y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            f(x, out=y)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / steps
+        res[f"fir_k{K}_r32"] = {"ms": round(sec * 1e3, 4), "gsps": round(n / sec / 1e9, 2),
+                                "tflops": round(2.0 * K * n / sec / 1e12, 2)}
+        f.close()
+    log(f"[bench] ops: {res}")
+    return res
 
 
 def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
@@ -363,7 +413,7 @@ def main():
     if not args.no_forms:
         from oracle import Oracle
         o = Oracle()
-        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8"]
+        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8", "fp32/factored"]
         result["forms"] = {w.name: forms_table(w, forms, max(5, args.steps // 2), 2, torch, o, 24)}
         del xd
         wd = workloads.wide_dynamic_range()
@@ -380,6 +430,8 @@ def main():
         del fout, xd
         fplan.close()
 
+    if not args.no_forms:
+        result["ops"] = ops_bench(torch)
     if not args.no_batched:
         log("[bench] batched ragged workload")
         result["batched"] = batched_bench(torch)

@@ -90,8 +90,10 @@ typedef enum tina_precision {
 } tina_precision;
 
 typedef enum tina_output {
-    TINA_OUT_PFB = 0,     /* channelizer output: frames x K complex64 */
-    TINA_OUT_FIR_ONLY = 1 /* polyphase FIR output only: frames x P samples of the input type */
+    TINA_OUT_PFB = 0,      /* channelizer output: frames x K complex64 */
+    TINA_OUT_FIR_ONLY = 1, /* polyphase FIR output only: frames x P samples of the input type */
+    TINA_OUT_INVERSE = 2   /* synthesis bank (tina_pfb_synthesize): channel frames -> samples;
+                              complex64 only, precision FP32, BF16 or BF16X3, dense DFT */
 } tina_output;
 
 typedef struct tina_pfb_desc {
@@ -110,7 +112,20 @@ typedef struct tina_pfb_desc {
                                   server, and tina_pfb_execute returns UNSUPPORTED).
                                   Descriptors whose struct_size ends before this field
                                   get the default. */
+    int32_t dft_algorithm;     /* tina_dft_algorithm (descriptors ending before this field:
+                                  TINA_DFT_DENSE) */
+    int32_t reserved_;         /* must be 0 */
 } tina_pfb_desc;
+
+/* How the DFT across branches is computed (both give the DFT of Eq. (12)):
+ *   TINA_DFT_DENSE     the dense matrix product X = Y F on the MFMA units, in the
+ *                      plan's precision (the paper's pointwise-convolution mapping);
+ *   TINA_DFT_FACTORED  a factored (four-step) DFT, P = P1 * P2: P2 DFTs of size
+ *                      P1, twiddles, P1 DFTs of size P2, each size-P1/P2 DFT a
+ *                      small matrix product on the MFMA units in FP32 -- 8 P (P1 + P2)
+ *                      flops per frame instead of 8 P^2.  FP32 only; 256 <= P <= 4096;
+ *                      single-stream execute only (not in batches or a server). */
+typedef enum tina_dft_algorithm { TINA_DFT_DENSE = 0, TINA_DFT_FACTORED = 1 } tina_dft_algorithm;
 
 typedef struct tina_pfb_plan_s* tina_pfb_plan_t;
 typedef struct tina_pfb_state_s* tina_pfb_state_t;
@@ -175,6 +190,23 @@ tina_status tina_pfb_output_frames(tina_pfb_plan_t plan, tina_pfb_state_t state,
 tina_status tina_pfb_execute(tina_pfb_plan_t plan, const void* d_in, int64_t n_samples,
                              void* d_out, int64_t out_capacity_frames,
                              tina_pfb_state_t state, int64_t* frames_written, void* stream);
+
+/*
+ * Synthesis (inverse) filter bank of a TINA_OUT_INVERSE plan: for n_frames
+ * frames of P complex64 channel values at d_X (device, row-major, 16-byte
+ * aligned), the
+ * inverse DFT of each frame (Sec. 4.2, Eq. (14): angle +2 pi p k / P, scaled
+ * by 1/P) as a matrix product on the MFMA units, then the polyphase FIR of
+ * Eq. (20) across frames with synthesis taps g_p(m) = h[m P + p] (each
+ * analysis branch filter reversed in time).  Output: n_frames * P complex64
+ * samples at d_out (device); out_capacity_samples must be at least that.
+ * With a state (created from this plan), the (M-1)*P inverse-DFT samples
+ * of the previous call are the history, and the state is updated on
+ * `stream`; without one the history is zero.  Asynchronous on `stream`.
+ */
+tina_status tina_pfb_synthesize(tina_pfb_plan_t plan, const void* d_X, int64_t n_frames, void* d_out,
+                                int64_t out_capacity_samples, tina_pfb_state_t state, int64_t* samples_written,
+                                void* stream);
 
 /* Per-stream filter state: (M-1)*P history samples plus fewer than P
  * residue samples, in device memory owned by the state.  Created zeroed. */

@@ -65,6 +65,8 @@ def _load(path: str | None = None):
     lib.oracle_dft.restype = i
     lib.oracle_pfb.argtypes = [i64, i64, i, vp, vp, i64, i64, vp, vp, vp]
     lib.oracle_pfb.restype = i
+    lib.oracle_idft.argtypes = [i64, vp, i64, vp]
+    lib.oracle_idft.restype = i
     if path is None:
         _lib = lib
     return lib
@@ -148,6 +150,33 @@ class Oracle:
         if self.lib.oracle_dft(P, int(cplx), self._ptr(flat), y.shape[0], self._ptr(X)) != 0:
             raise ValueError("oracle_dft failed")
         return X
+
+    def idft(self, X) -> np.ndarray:
+        """Inverse DFT of each row of X (frames x P complex), Sec. 4.2."""
+        X = np.ascontiguousarray(X, dtype=np.complex128)
+        P = X.shape[1]
+        v = np.empty_like(X)
+        if self.lib.oracle_idft(P, self._ptr(X.view(np.float64)), X.shape[0], self._ptr(v.view(np.float64))) != 0:
+            raise ValueError("oracle_idft failed")
+        return v
+
+    @staticmethod
+    def synthesis_taps(h, P: int, M: int) -> np.ndarray:
+        """Prototype g' of the synthesis FIR: branch p's taps g_p(m) = h[m P + p]
+        (each analysis branch filter reversed in time), stored so that the
+        polyphase FIR reads g_p(m) = g'[(M-1-m) P + p]: the M length-P blocks of
+        h in reverse order."""
+        return np.asarray(h, dtype=np.float64).reshape(M, P)[::-1].reshape(-1).copy()
+
+    def synthesize(self, X, P: int, M: int, h, hist=None) -> np.ndarray:
+        """Synthesis bank for complex channel frames X (frames x P): the inverse
+        DFT of each frame (Sec. 4.2), then the polyphase FIR of Eq. (20) across
+        frames with the synthesis taps g_p(m) = h[m P + p]; returns the
+        frames * P output samples.  `hist` = the (M-1) * P IDFT samples before
+        the first frame (zeros when None)."""
+        v = self.idft(X)
+        y = self.fir(v.reshape(-1), P, M, self.synthesis_taps(h, P, M), hist=hist)
+        return y.reshape(-1)
 
     def pfb(self, x, P: int, M: int, h, hist=None, frames=None, return_fir: bool = False):
         """Filter-bank output X (frames x K complex128), K = P/2+1 (real x) or P."""

@@ -254,6 +254,38 @@ int oracle_dft(int64_t P, int cplx, const double* y, int64_t nframes, double* X)
 }
 
 /*
+ * Inverse DFT of each frame (Sec. 4.2, Eq. (14): X = Z IF, the inverse
+ * Fourier matrix): v[p] = (1/P) sum_{k=0}^{P-1} X[k] (cos t + i sin t),
+ * t = 2 pi ((p k) mod P) / P.  Complex in, complex out (re, im doubles).
+ */
+int oracle_idft(int64_t P, const double* X, int64_t nframes, double* v) {
+    if (P < 1 || !X || !v) return -1;
+    double* tw = twiddle_table(P);
+    if (!tw) return -3;
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < nframes; ++f) {
+        const double* Xf = X + f * P * 2;
+        double* vf = v + f * P * 2;
+        for (int64_t p = 0; p < P; ++p) {
+            double re = 0.0, im = 0.0;
+            int64_t r = 0; /* (k * p) mod P */
+            for (int64_t k = 0; k < P; ++k) {
+                double c = tw[2 * r], s = tw[2 * r + 1];
+                double a = Xf[2 * k], b = Xf[2 * k + 1];
+                re += a * c - b * s;
+                im += a * s + b * c;
+                r += p;
+                if (r >= P) r -= P;
+            }
+            vf[2 * p] = re / (double)P;
+            vf[2 * p + 1] = im / (double)P;
+        }
+    }
+    free(tw);
+    return 0;
+}
+
+/*
  * The filter bank: for each requested frame, the polyphase FIR of Eq. (20)
  * followed by the DFT across its P branches.  Output X: K complex values
  * (re, im doubles) per requested frame.  If y_out is not NULL the FIR output

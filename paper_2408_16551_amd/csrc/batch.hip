@@ -152,6 +152,8 @@ tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vect
         const tina_pfb_plan_s* p = it.plan;
         if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: item " + std::to_string(i) + " has no plan");
         if (p->device != b->device) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: plan on another device");
+        if (p->dft_algorithm != TINA_DFT_DENSE)
+            return fail(TINA_ERR_UNSUPPORTED, "batch: plans with the factored DFT run through tina_pfb_execute only");
         if (p->output != TINA_OUT_PFB || p->precision != b->form)
             return fail(TINA_ERR_INVALID_ARGUMENT, "batch: every plan must be a filter-bank plan of the batch's precision");
         if (it.n_samples < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: negative sample count");

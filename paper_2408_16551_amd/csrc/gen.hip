@@ -74,8 +74,21 @@ __device__ inline uint8_t e4m3_bits_exact(double r) {
     return sgn | (uint8_t)((e + 7) << 3) | (uint8_t)mant;
 }
 
-// Value of Bt[n][k] in FP64.
-__device__ inline double dft_entry(int64_t n, int64_t k, int P, int cplx) {
+// Value of Bt[n][k] in FP64.  inverse: the inverse DFT of Sec. 4.2, Eq. (14)
+// (angle +2 pi p k / P, scaled by 1/P; complex frames only).
+__device__ inline double dft_entry(int64_t n, int64_t k, int P, int cplx, int inverse) {
+    if (inverse) {
+        const int64_t p = n >> 1, ch = k >> 1;  // output sample p, input channel ch
+        const int64_t r = (p * ch) % P;
+        double s, c;
+        sincospi(2.0 * (double)r / (double)P, &s, &c);
+        const int out_im = (int)(n & 1), in_im = (int)(k & 1);
+        // (a + ib)(c + is) / P: re = (a c - b s) / P, im = (a s + b c) / P
+        double v;
+        if (out_im == in_im) v = c;
+        else v = in_im ? -s : s;
+        return v / (double)P;
+    }
     if (!cplx) {
         if (n == 0) return 1.0;
         if (n == 1) return (k & 1) ? -1.0 : 1.0;
@@ -95,13 +108,13 @@ __device__ inline double dft_entry(int64_t n, int64_t k, int P, int cplx) {
 }
 
 template <int FORM>
-__global__ void dft_operand_kernel(void* piece0, void* piece1, int P, int cplx) {
+__global__ void dft_operand_kernel(void* piece0, void* piece1, int P, int cplx, int inverse) {
     const int64_t N = cplx ? 2 * (int64_t)P : P;
     const int64_t K = N;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N * K) return;
     const int64_t n = idx / K, k = idx % K;
-    const double v = dft_entry(n, k, P, cplx);
+    const double v = dft_entry(n, k, P, cplx, inverse);
     if constexpr (FORM == FORM_FP32) {
         ((float*)piece0)[idx] = __double2float_rn(v);
     } else if constexpr (FORM == FORM_BF16 || FORM == FORM_BF16X3) {
@@ -118,6 +131,14 @@ __global__ void dft_operand_kernel(void* piece0, void* piece1, int P, int cplx) 
     }
 }
 
+// Block-reversed FP32 taps of the synthesis FIR: g'[(M-1-m) P + p] = h[m P + p].
+__global__ void synthesis_taps_kernel(const double* h64, float* g32, int P, int M) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)P * M) return;
+    const int64_t b = j / P, p = j % P;
+    g32[j] = __double2float_rn(h64[(M - 1 - b) * P + p]);
+}
+
 }  // namespace
 
 hipError_t launch_window(double* h64, float* h32, int P, int M, int window, hipStream_t s) {
@@ -132,17 +153,23 @@ hipError_t launch_taps_to_f32(const double* h64, float* h32, int64_t L, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int cplx, int form, hipStream_t s) {
+hipError_t launch_synthesis_taps(const double* h64, float* g32, int P, int M, hipStream_t s) {
+    const int64_t L = (int64_t)P * M;
+    hipLaunchKernelGGL(synthesis_taps_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, h64, g32, P, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int cplx, int form, hipStream_t s, int inverse) {
     const int64_t N = cplx ? 2 * (int64_t)P : P;
     const int64_t total = N * N;
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
     switch (form) {
-        case FORM_FP32: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP32>, grid, block, 0, s, piece0, piece1, P, cplx); break;
-        case FORM_BF16: hipLaunchKernelGGL(dft_operand_kernel<FORM_BF16>, grid, block, 0, s, piece0, piece1, P, cplx); break;
-        case FORM_BF16X3: hipLaunchKernelGGL(dft_operand_kernel<FORM_BF16X3>, grid, block, 0, s, piece0, piece1, P, cplx); break;
-        case FORM_FP16: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP16>, grid, block, 0, s, piece0, piece1, P, cplx); break;
-        case FORM_FP16X3: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP16X3>, grid, block, 0, s, piece0, piece1, P, cplx); break;
-        case FORM_FP8: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP8>, grid, block, 0, s, piece0, piece1, P, cplx); break;
+        case FORM_FP32: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP32>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
+        case FORM_BF16: hipLaunchKernelGGL(dft_operand_kernel<FORM_BF16>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
+        case FORM_BF16X3: hipLaunchKernelGGL(dft_operand_kernel<FORM_BF16X3>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
+        case FORM_FP16: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP16>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
+        case FORM_FP16X3: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP16X3>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
+        case FORM_FP8: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP8>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

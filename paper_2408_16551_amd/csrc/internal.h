@@ -30,7 +30,9 @@ hipError_t launch_taps_to_f32(const double* h64, float* h32, int64_t L, hipStrea
 // DFT operand Bt[N][K] (row n = output column, K contiguous) in the pieces of
 // `form`: piece0 (and piece1 for split forms), element size form_elem_bytes.
 hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int complex_input, int form,
-                              hipStream_t s);
+                              hipStream_t s, int inverse = 0);
+// Block-reversed FP32 taps of the synthesis FIR.
+hipError_t launch_synthesis_taps(const double* h64, float* g32, int P, int M, hipStream_t s);
 
 // ----------------------------------------------------------------------- FIR
 struct FirArgs {
@@ -74,6 +76,23 @@ struct GemmArgs {
     int32_t form;
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------- factored DFT
+struct FftArgs {
+    const float* y;        // FIR output [F][ldy] (P real or P complex values per frame)
+    int64_t ldy;
+    int64_t F;
+    const float* mat1;     // realified DFT_{P1} (2 P1 x 2 P1)
+    const float* mat3;     // realified DFT_{P2} (2 P2 x 2 P2); unused when P1 == P2
+    const float* tw;       // cos, sin of 2 pi r / P
+    float* out;            // output rows (complex64), row stride ldo floats
+    int64_t ldo;
+    int32_t P, cplx, cus;
+};
+bool fft_supported(int P);
+void fft_factors(int P, int& P1, int& P2);
+hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStream_t s);
+hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s);
 
 // --------------------------------------------------------------- batched path
 // One item of a batched launch: the FIR and GEMM arguments of one stream

@@ -13,6 +13,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,14 +41,17 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     *out = nullptr;
     if (d->struct_size < offsetof(tina_pfb_desc, workspace_bytes))
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
-    const int64_t ws_req = d->struct_size >= sizeof(tina_pfb_desc) ? d->workspace_bytes : 0;
+    const int64_t ws_req = d->struct_size >= offsetof(tina_pfb_desc, dft_algorithm) ? d->workspace_bytes : 0;
+    const int dft_alg = d->struct_size >= offsetof(tina_pfb_desc, reserved_) ? d->dft_algorithm : TINA_DFT_DENSE;
+    if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown dft_algorithm");
     if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
     if (d->window < TINA_WINDOW_RECT || d->window > TINA_WINDOW_CUSTOM)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown window");
-    if (d->output != TINA_OUT_PFB && d->output != TINA_OUT_FIR_ONLY)
+    if (d->output != TINA_OUT_PFB && d->output != TINA_OUT_FIR_ONLY && d->output != TINA_OUT_INVERSE)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown output");
-    if (d->output == TINA_OUT_PFB && (d->precision < TINA_PREC_FP32 || d->precision > TINA_PREC_FP8_FRAME))
+    if (d->output != TINA_OUT_FIR_ONLY && (d->precision < TINA_PREC_FP32 || d->precision > TINA_PREC_FP8_FRAME))
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown precision");
     if (d->window == TINA_WINDOW_CUSTOM && !d->custom_taps)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: CUSTOM window without custom_taps");
@@ -55,6 +59,13 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     if (!is_pow2(d->channels) || d->channels < 16 || d->channels > 8192)
         return fail(TINA_ERR_UNSUPPORTED, "plan: channels must be a power of two in [16, 8192]");
     if (d->taps > 64) return fail(TINA_ERR_UNSUPPORTED, "plan: taps must be in [1, 64]");
+    if (d->output == TINA_OUT_INVERSE &&
+        (d->sample_type != TINA_SAMPLE_C64 || dft_alg != TINA_DFT_DENSE ||
+         !(d->precision == TINA_PREC_FP32 || d->precision == TINA_PREC_BF16 || d->precision == TINA_PREC_BF16X3)))
+        return fail(TINA_ERR_UNSUPPORTED, "plan: the synthesis bank needs complex64, the dense DFT and FP32, BF16 or BF16X3");
+    if (dft_alg == TINA_DFT_FACTORED && d->output == TINA_OUT_PFB &&
+        (d->precision != TINA_PREC_FP32 || !fft_supported(d->channels)))
+        return fail(TINA_ERR_UNSUPPORTED, "plan: the factored DFT needs FP32 and 256 <= channels <= 4096");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TINA_ERR_DEVICE, "plan: no HIP device");
     if (d->device < 0 || d->device >= ndev) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: bad device ordinal");
@@ -71,11 +82,17 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     p->cf = d->sample_type == TINA_SAMPLE_C64 ? 2 : 1;
     p->W = p->P * p->cf;
     p->window = d->window;
-    p->precision = d->output == TINA_OUT_PFB ? d->precision : TINA_PREC_FP32;
+    p->precision = d->output != TINA_OUT_FIR_ONLY ? d->precision : TINA_PREC_FP32;
     p->output = d->output;
+    p->dft_algorithm = d->output == TINA_OUT_PFB ? dft_alg : TINA_DFT_DENSE;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, d->device) == hipSuccess && prop.multiProcessorCount > 0)
+            p->cus = prop.multiProcessorCount;
+    }
     p->K = p->W;
     p->N = p->W;
-    p->kout = d->output == TINA_OUT_FIR_ONLY ? p->P : (p->cf == 2 ? p->P : p->P / 2 + 1);
+    p->kout = d->output != TINA_OUT_PFB ? p->P : (p->cf == 2 ? p->P : p->P / 2 + 1);
 
     auto bail = [&](tina_status st, const std::string& m) {
         p->release();
@@ -94,12 +111,32 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     }
     if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: taps: ") + hipGetErrorString(e));
 
-    if (p->output == TINA_OUT_PFB) {
+    if (p->output != TINA_OUT_FIR_ONLY) {
         const int form = p->precision;
-        const int64_t nbytes = (int64_t)p->N * p->K * form_elem_bytes(form);
-        for (int i = 0; i < form_pieces(form); ++i)
-            if (hipMalloc(&p->B[i], nbytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: DFT operand allocation");
-        e = launch_dft_operand(p->B[0], p->B[1], p->P, p->cf == 2, form, nullptr);
+        if (p->output == TINA_OUT_INVERSE) {
+            const int64_t nbytes = (int64_t)p->N * p->K * form_elem_bytes(form);
+            for (int i = 0; i < form_pieces(form); ++i)
+                if (hipMalloc(&p->B[i], nbytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: IDFT operand allocation");
+            if (hipMalloc(&p->g32, L * sizeof(float)) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: synthesis taps");
+            for (int i = 0; i < 2; ++i)
+                if (hipMalloc(&p->hist[i], std::max<int64_t>(1, (int64_t)(p->M - 1) * p->W) * sizeof(float)) != hipSuccess)
+                    return bail(TINA_ERR_OUT_OF_MEMORY, "plan: synthesis history");
+            e = launch_dft_operand(p->B[0], p->B[1], p->P, 1, form, nullptr, /*inverse=*/1);
+            if (e == hipSuccess) e = launch_synthesis_taps(p->h64, p->g32, p->P, p->M, nullptr);
+        } else if (p->dft_algorithm == TINA_DFT_FACTORED) {
+            int P1, P2;
+            fft_factors(p->P, P1, P2);
+            if (hipMalloc(&p->fft_mat1, sizeof(float) * 4 * P1 * P1) != hipSuccess ||
+                (P1 != P2 && hipMalloc(&p->fft_mat3, sizeof(float) * 4 * P2 * P2) != hipSuccess) ||
+                hipMalloc(&p->fft_tw, sizeof(float) * 2 * p->P) != hipSuccess)
+                return bail(TINA_ERR_OUT_OF_MEMORY, "plan: factored DFT tables");
+            e = launch_fft_tables(p->fft_mat1, p->fft_mat3, p->fft_tw, p->P, nullptr);
+        } else {
+            const int64_t nbytes = (int64_t)p->N * p->K * form_elem_bytes(form);
+            for (int i = 0; i < form_pieces(form); ++i)
+                if (hipMalloc(&p->B[i], nbytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "plan: DFT operand allocation");
+            e = launch_dft_operand(p->B[0], p->B[1], p->P, p->cf == 2, form, nullptr);
+        }
         if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: DFT operand: ") + hipGetErrorString(e));
         const int64_t ws_bytes = ws_req == 0 ? kWorkspaceBytes : ws_req;
         p->ch_frames = ws_bytes > 0 ? ws_bytes / ((int64_t)p->W * 4) : 0;
@@ -167,6 +204,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
                                                          " frames) below frame count " + std::to_string(F));
     if (p->output == TINA_OUT_PFB && p->ch_frames == 0)
         return fail(TINA_ERR_UNSUPPORTED, "execute: plan was created without a workspace (batch/server use only)");
+    if (p->output == TINA_OUT_INVERSE) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: synthesis plans run through tina_pfb_synthesize");
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute: hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
@@ -216,6 +254,22 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.F = Fc;
             fa.amax = form_scaled(form) ? p->amax : nullptr;
             HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
+            if (p->dft_algorithm == TINA_DFT_FACTORED) {
+                FftArgs xa{};
+                xa.y = p->ws;
+                xa.ldy = p->W;
+                xa.F = Fc;
+                xa.mat1 = p->fft_mat1;
+                xa.mat3 = p->fft_mat3;
+                xa.tw = p->fft_tw;
+                xa.out = (float*)d_out + c0 * ldo;
+                xa.ldo = ldo;
+                xa.P = p->P;
+                xa.cplx = p->cf == 2;
+                xa.cus = p->cus;
+                HIP_TRY(timed(p->ev_dft, [&] { return launch_fft_dft(xa, s); }));
+                continue;
+            }
             GemmArgs ga{};
             ga.A = p->ws;
             ga.lda = p->W;
@@ -271,6 +325,66 @@ tina_status tina_pfb_profile_read(tina_pfb_plan_t p, double* fir_ms, int64_t* fi
     tina_status st = sum(p->ev_fir, fir_ms, fir_n);
     if (st != TINA_OK) return st;
     return sum(p->ev_dft, dft_ms, dft_n);
+}
+
+tina_status tina_pfb_synthesize(tina_pfb_plan_t p, const void* d_X, int64_t F, void* d_out, int64_t cap,
+                                tina_pfb_state_t st, int64_t* written, void* stream) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: NULL plan");
+    if (p->output != TINA_OUT_INVERSE) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: not a synthesis plan");
+    if (F < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: negative frame count");
+    if (F > 0 && (!d_X || !d_out)) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: NULL buffer");
+    if (st && st->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: state belongs to another plan");
+    if ((uintptr_t)d_X % 16 || (uintptr_t)d_out % 8)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: d_X must be 16-byte and d_out 8-byte aligned");
+    if (F * p->P > cap) return fail(TINA_ERR_INVALID_ARGUMENT, "synthesize: output capacity below frames * P samples");
+    if (p->ch_frames == 0) return fail(TINA_ERR_UNSUPPORTED, "synthesize: plan was created without a workspace");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "synthesize: hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t hist_floats = (int64_t)(p->M - 1) * p->W;
+    const float* prefix = st ? st->buf[st->cur] : nullptr;
+    int scratch = 0;
+    for (int64_t c0 = 0; c0 < F; c0 += p->ch_frames) {
+        const int64_t Fc = F - c0 < p->ch_frames ? F - c0 : p->ch_frames;
+        GemmArgs ga{};  // inverse DFT of the frames into the workspace
+        ga.A = (const float*)d_X + c0 * p->W;
+        ga.lda = p->W;
+        ga.B0 = p->B[0];
+        ga.B1 = p->B[1];
+        ga.out = p->ws;
+        ga.ldo = p->W;
+        ga.F = Fc;
+        ga.K = p->K;
+        ga.N = p->N;
+        ga.real_pack = 0;
+        ga.form = p->precision;
+        HIP_TRY(launch_dft_gemm(ga, s));
+        FirArgs fa{};  // synthesis FIR across frames
+        fa.prefix = prefix;
+        fa.plen = hist_floats;
+        fa.chunk = p->ws;
+        fa.nchunk = Fc * p->W;
+        fa.taps = p->g32;
+        fa.y = (float*)d_out + c0 * p->W;
+        fa.ldy = p->W;
+        fa.g0 = 0;
+        fa.F = Fc;
+        fa.W = p->W;
+        fa.P = p->P;
+        fa.M = p->M;
+        fa.cf = p->cf;
+        HIP_TRY(launch_fir(fa, s));
+        // History for the next piece (or the state): the last M-1 frames of prefix ++ workspace.
+        const bool last = c0 + Fc >= F;
+        if (last && !st) break;
+        float* dst = last ? st->buf[st->cur ^ 1] : p->hist[scratch];
+        HIP_TRY(launch_gather_ext(prefix, hist_floats, p->ws, Fc * p->W, dst, Fc * p->W, hist_floats, s));
+        prefix = dst;
+        scratch ^= 1;
+    }
+    if (st && F > 0) st->cur ^= 1;
+    if (written) *written = F * p->P;
+    return TINA_OK;
 }
 
 tina_status tina_pfb_state_create(tina_pfb_plan_t p, tina_pfb_state_t* out) {

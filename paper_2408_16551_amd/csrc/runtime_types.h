@@ -44,6 +44,13 @@ struct tina_pfb_plan_s {
     double* h64 = nullptr;
     float* h32 = nullptr;
     void* B[2] = {nullptr, nullptr};
+    int dft_algorithm = 0;
+    float* fft_mat1 = nullptr;  // factored DFT tables
+    float* fft_mat3 = nullptr;
+    float* fft_tw = nullptr;
+    float* g32 = nullptr;       // synthesis FIR taps (inverse plans)
+    float* hist[2] = {nullptr, nullptr};  // history scratch between workspace pieces (inverse plans)
+    int cus = 256;
     float* ws = nullptr;
     float* amax = nullptr;
     int64_t ch_frames = 0;
@@ -72,9 +79,12 @@ struct tina_pfb_plan_s {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         clear_events();
-        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax})
+        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax, (void*)fft_mat1, (void*)fft_mat3,
+                        (void*)fft_tw, (void*)g32, (void*)hist[0], (void*)hist[1]})
             if (p) (void)hipFree(p);
+        g32 = hist[0] = hist[1] = nullptr;
         h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr;
+        fft_mat1 = fft_mat3 = fft_tw = nullptr;
     }
 };
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtina_pfb.so")
 SAMPLE = {"r32": 0, "c64": 1}
 WINDOW = {"rect": 0, "hann": 1, "hamming": 2, "blackman": 3, "custom": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5}
-OUTPUT = {"pfb": 0, "fir": 1}
+OUTPUT = {"pfb": 0, "fir": 1, "inverse": 2}
 
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
           5: "BUSY", 6: "NOT_READY", 7: "TOO_LARGE", 8: "TIMEOUT", 9: "CANCELLED"}
@@ -26,7 +26,7 @@ STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 
 EXPORTS = [
     "tina_last_error", "tina_version",
     "tina_pfb_plan", "tina_pfb_plan_destroy", "tina_pfb_channels_out", "tina_pfb_plan_taps",
-    "tina_pfb_output_frames", "tina_pfb_execute",
+    "tina_pfb_output_frames", "tina_pfb_execute", "tina_pfb_synthesize",
     "tina_pfb_state_create", "tina_pfb_state_destroy", "tina_pfb_state_reset", "tina_pfb_state_size",
     "tina_pfb_state_export", "tina_pfb_state_import",
     "tina_pfb_profile_enable", "tina_pfb_profile_read",
@@ -34,6 +34,7 @@ EXPORTS = [
     "tina_pfb_batch_split_units",
     "tina_server_create", "tina_server_destroy", "tina_server_stream_create", "tina_pfb_submit", "tina_pfb_poll",
     "tina_pfb_wait", "tina_pfb_cancel", "tina_server_get_stats", "tina_server_arena_simulate",
+    "tina_unfold", "tina_fir_create", "tina_fir_destroy", "tina_fir_execute",
 ]
 
 
@@ -80,7 +81,8 @@ class _Desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("channels", ctypes.c_int32), ("taps", ctypes.c_int32),
                 ("sample_type", ctypes.c_int32), ("window", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("output", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("custom_taps", ctypes.POINTER(ctypes.c_double)), ("workspace_bytes", ctypes.c_int64)]
+                ("custom_taps", ctypes.POINTER(ctypes.c_double)), ("workspace_bytes", ctypes.c_int64),
+                ("dft_algorithm", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 _lib = None
@@ -105,6 +107,7 @@ def load(path: str = LIB_PATH):
         "tina_pfb_plan_taps": ([vp, vp], i32),
         "tina_pfb_output_frames": ([vp, vp, i64, P64], i32),
         "tina_pfb_execute": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
+        "tina_pfb_synthesize": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
         "tina_pfb_state_create": ([vp, ctypes.POINTER(vp)], i32),
         "tina_pfb_state_destroy": ([vp], i32),
         "tina_pfb_state_reset": ([vp], i32),
@@ -125,6 +128,10 @@ def load(path: str = LIB_PATH):
         "tina_pfb_cancel": ([vp, ctypes.c_uint64], i32),
         "tina_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
         "tina_server_arena_simulate": ([i64, vp, i32, vp, P64], i32),
+        "tina_unfold": ([vp, i64, i64, i64, vp, i64, P64, vp], i32),
+        "tina_fir_create": ([i32, vp, i32, i32, ctypes.POINTER(vp)], i32),
+        "tina_fir_destroy": ([vp], i32),
+        "tina_fir_execute": ([vp, vp, i64, vp, vp], i32),
         "tina_pfb_batch_execute": ([vp, ctypes.POINTER(_Work), i32, vp], i32),
         "tina_pfb_batch_tune": ([vp, ctypes.POINTER(_Work), i32, vp, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int32)], i32),
@@ -154,7 +161,7 @@ class Plan:
 
     def __init__(self, channels: int, taps: int, sample_type: str = "r32", window: str = "hann",
                  precision: str = "fp32", output: str = "pfb", device: int = 0, custom_taps=None,
-                 workspace_bytes: int = 0):
+                 workspace_bytes: int = 0, dft: str = "dense"):
         lib = load()
         self.P, self.M = int(channels), int(taps)
         self.sample_type, self.precision, self.output = sample_type, precision, output
@@ -165,6 +172,7 @@ class Plan:
         d.sample_type, d.window = SAMPLE[sample_type], WINDOW[window]
         d.precision, d.output, d.device = PRECISION[precision], OUTPUT[output], int(device)
         d.workspace_bytes = int(workspace_bytes)
+        d.dft_algorithm = {"dense": 0, "factored": 1}[dft]
         self._custom = None
         if custom_taps is not None:
             self._custom = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -241,6 +249,21 @@ class Plan:
         return out[: fw.value]
 
     __call__ = execute
+
+    def synthesize(self, X, out=None, state: "State | None" = None, stream=None):
+        """Synthesis bank of an output="inverse" plan: X (frames x P complex64
+        device tensor) -> frames * P complex64 samples."""
+        import torch
+        if X.dtype != torch.complex64 or X.dim() != 2 or X.shape[1] != self.P or not X.is_cuda or not X.is_contiguous():
+            raise ValueError("X must be a contiguous frames x P complex64 CUDA tensor")
+        F = X.shape[0]
+        if out is None:
+            out = torch.empty(F * self.P, dtype=torch.complex64, device=X.device)
+        n = ctypes.c_int64()
+        check(load().tina_pfb_synthesize(self.handle, ctypes.c_void_p(X.data_ptr() if F else 0), F,
+                                         ctypes.c_void_p(out.data_ptr() if out.numel() else 0), out.numel(),
+                                         state.handle if state else None, ctypes.byref(n), _stream_handle(stream)))
+        return out[: n.value]
 
 
 class State:
@@ -448,3 +471,54 @@ class Server:
         s = _ServerStats()
         check(load().tina_server_get_stats(self.handle, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+
+def unfold(x, width: int, stride: int = 1, out=None, stream=None):
+    """Sliding-window unfold Y[i][j] = x[i*stride + j] of a 1-D float32 device
+    tensor; returns the rows x width tensor."""
+    import torch
+    if x.dtype != torch.float32 or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous 1-D float32 CUDA tensor")
+    n = x.numel()
+    rows = 0 if n < width else (n - width) // stride + 1
+    if out is None:
+        out = torch.empty((rows, width), dtype=torch.float32, device=x.device)
+    got = ctypes.c_int64()
+    check(load().tina_unfold(ctypes.c_void_p(x.data_ptr() if n else 0), n, int(width), int(stride),
+                             ctypes.c_void_p(out.data_ptr() if out.numel() else 0), out.shape[0] if out.dim() == 2 else 0,
+                             ctypes.byref(got), _stream_handle(stream)))
+    return out[: got.value]
+
+
+class Fir:
+    """FIR filter y[i] = sum_k a[k] x[i-k] with arbitrary taps (host doubles)."""
+
+    def __init__(self, taps, sample_type: str = "r32", device: int = 0):
+        a = np.ascontiguousarray(taps, dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(load().tina_fir_create(int(device), a.ctypes.data_as(ctypes.c_void_p), a.size, SAMPLE[sample_type],
+                                     ctypes.byref(h)))
+        self.handle = h
+        self.complex_input = sample_type == "c64"
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tina_fir_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        want = torch.complex64 if self.complex_input else torch.float32
+        if x.dtype != want or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous 1-D {want} CUDA tensor")
+        if out is None:
+            out = torch.empty_like(x)
+        check(load().tina_fir_execute(self.handle, ctypes.c_void_p(x.data_ptr() if x.numel() else 0), x.numel(),
+                                      ctypes.c_void_p(out.data_ptr() if out.numel() else 0), _stream_handle(stream)))
+        return out

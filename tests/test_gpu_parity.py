@@ -276,3 +276,102 @@ def test_full_size_wide_dynamic_range_sampled(oracle, precision, wide_wl):
     err = rel_l2(got, ref)
     print(f"wide dynamic range {precision}: rel_l2={err:.3e}")
     assert err < (FP32_BOUND if precision == "fp32" else REDUCED_BOUNDS[precision])
+
+
+# ---------------------------------------------------------------- factored DFT
+@pytest.mark.parametrize("P,M,cplx,frames", [(256, 8, True, 130), (512, 11, False, 75), (1024, 16, False, 200),
+                                              (1024, 16, True, 61), (2048, 5, True, 33), (4096, 8, True, 70),
+                                              (4096, 3, False, 40)])
+def test_factored_dft_matches_oracle(oracle, P, M, cplx, frames):
+    from paper_2408_16551_amd.pfb import Plan
+    N = P * frames + P // 3
+    x = _rand(N, cplx, seed=17 * P + M)
+    plan = Plan(P, M, "c64" if cplx else "r32", "hann", "fp32", dft="factored")
+    X = _run(plan, x)
+    ref = oracle.pfb(x[: (N // P) * P], P, M, oracle.window(P, M, "hann"))
+    err = rel_l2(X, ref)
+    print(f"factored P={P} M={M} cplx={cplx}: rel_l2={err:.3e}")
+    assert err < FP32_BOUND
+    if not cplx:
+        assert np.all(X[:, 0].imag == 0) and np.all(X[:, -1].imag == 0)
+
+
+def test_factored_dft_streaming_bitwise():
+    from paper_2408_16551_amd.pfb import Plan, State
+    P, M = 1024, 12
+    N = P * 90 + 77
+    x = _rand(N, True, seed=5)
+    plan = Plan(P, M, "c64", "hann", "fp32", dft="factored")
+    one = _run(plan, x)
+    st = State(plan)
+    cuts = [0, 500, P * 7, P * 50 + 3, N]
+    got = np.concatenate([_run(plan, np.ascontiguousarray(x[a:b]), state=st) for a, b in zip(cuts[:-1], cuts[1:])])
+    assert np.array_equal(got, one)
+
+
+def test_factored_rejects_unsupported():
+    from paper_2408_16551_amd.pfb import Plan, TinaError
+    for kw in [dict(channels=8192, precision="fp32"), dict(channels=1024, precision="bf16x3"),
+               dict(channels=128, precision="fp32")]:
+        with pytest.raises(TinaError) as e:
+            Plan(kw["channels"], 8, "c64", "hann", kw["precision"], dft="factored")
+        assert e.value.status == 2
+
+
+def test_full_size_wide_dynamic_range_factored_sampled(oracle, wide_wl):
+    from paper_2408_16551_amd.pfb import Plan
+    w = wide_wl
+    plan = Plan(w.P, w.M, "c64", w.window, "fp32", dft="factored")
+    X = plan(_dev(w.x))
+    torch.cuda.synchronize()
+    F = w.x.size // w.P
+    fr = _sample_frames(F, w.M, 24, seed=2)
+    got = X[torch.from_numpy(fr).cuda()].cpu().numpy()
+    key = ("wide", fr.tobytes())
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.pfb(w.x, w.P, w.M, oracle.window(w.P, w.M, w.window), frames=fr)
+    assert rel_l2(got, _ORACLE_CACHE[key]) < FP32_BOUND
+
+
+# ------------------------------------------------------- synthesis (inverse) bank
+@pytest.mark.parametrize("P,M,F,precision", [(64, 5, 120, "fp32"), (1024, 16, 70, "fp32"), (4096, 8, 30, "fp32"),
+                                             (256, 12, 200, "bf16x3"), (512, 1, 50, "fp32")])
+def test_synthesis_matches_oracle(oracle, P, M, F, precision):
+    from paper_2408_16551_amd.pfb import Plan
+    g = np.random.Generator(np.random.PCG64(P + M))
+    X = (g.standard_normal((F, P)) + 1j * g.standard_normal((F, P))).astype(np.complex64)
+    plan = Plan(P, M, "c64", "hann", precision, "inverse")
+    xh = plan.synthesize(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.synthesize(X, P, M, oracle.window(P, M, "hann"))
+    err = rel_l2(xh.cpu().numpy(), ref)
+    print(f"synthesis {precision} P={P} M={M}: rel_l2={err:.3e}")
+    assert err < (FP32_BOUND if precision == "fp32" else REDUCED_BOUNDS[precision])
+
+
+def test_analysis_then_synthesis_unit_bank_reconstructs():
+    from paper_2408_16551_amd.pfb import Plan
+    P = 256
+    x = _rand(P * 100, True, seed=31)
+    ana = Plan(P, 1, "c64", "custom", "fp32", custom_taps=np.ones(P))
+    syn = Plan(P, 1, "c64", "custom", "fp32", "inverse", custom_taps=np.ones(P))
+    X = ana(_dev(x))
+    xh = syn.synthesize(X).cpu().numpy()
+    assert rel_l2(xh, x) < 1e-6
+
+
+def test_synthesis_streaming_and_pieces_bitwise():
+    from paper_2408_16551_amd.pfb import Plan, State
+    P, M, F = 128, 7, 300
+    g = np.random.Generator(np.random.PCG64(8))
+    X = (g.standard_normal((F, P)) + 1j * g.standard_normal((F, P))).astype(np.complex64)
+    Xd = torch.from_numpy(X).cuda()
+    plan = Plan(P, M, "c64", "hann", "fp32", "inverse")
+    one = plan.synthesize(Xd).cpu().numpy()
+    # a small workspace forces several pieces inside one call
+    small = Plan(P, M, "c64", "hann", "fp32", "inverse", workspace_bytes=128 * 2 * P * 4 // 2)
+    assert np.array_equal(small.synthesize(Xd).cpu().numpy(), one)
+    st = State(plan)
+    parts = [plan.synthesize(Xd[a:b].contiguous(), state=st).cpu().numpy()
+             for a, b in [(0, 1), (1, 50), (50, 51), (51, 300)]]
+    assert np.array_equal(np.concatenate(parts), one)

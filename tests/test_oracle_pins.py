@@ -287,3 +287,43 @@ def test_frame_subset_equals_full(oracle):
     full = oracle.pfb(x, P, M, h)
     fr = np.array([0, 7, 39, 12])
     assert np.array_equal(oracle.pfb(x, P, M, h, frames=fr), full[fr])
+
+
+# --------------------------------------------------------------------------
+# Synthesis (inverse) bank: IDFT (Sec. 4.2, Eq. (14)) then polyphase FIR.
+# --------------------------------------------------------------------------
+def test_idft_matches_numpy_and_inverts_dft(oracle):
+    g = _rng(21)
+    y = g.standard_normal((6, 64)) + 1j * g.standard_normal((6, 64))
+    v = oracle.idft(y)
+    assert np.linalg.norm(v - np.fft.ifft(y, axis=1)) / np.linalg.norm(v) < 1e-13
+    assert np.max(np.abs(oracle.idft(oracle.dft(y)) - y)) < 1e-12
+
+
+def test_synthesis_inverts_single_tap_unit_bank(oracle):
+    # M = 1 with unit taps: analysis is the framed DFT, synthesis its inverse.
+    P = 32
+    x = _rng(22).standard_normal(P * 40) + 1j * _rng(23).standard_normal(P * 40)
+    X = oracle.pfb(x, P, 1, np.ones(P))
+    assert np.max(np.abs(oracle.synthesize(X, P, 1, np.ones(P)) - x)) < 1e-12
+
+
+@pytest.mark.parametrize("P,M", [(8, 3), (16, 4)])
+def test_analysis_then_synthesis_is_branchwise_convolution(oracle, P, M):
+    # The IDFT undoes the DFT, so analysis -> synthesis filters branch p by
+    # h_p then g_p: x_hat_p = g_p * h_p * x_p (brute force with np.convolve).
+    g = _rng(24)
+    h = g.standard_normal(P * M)
+    F = 30
+    x = g.standard_normal(F * P) + 1j * g.standard_normal(F * P)
+    xh = oracle.synthesize(oracle.pfb(x, P, M, h), P, M, h)
+    for p in range(P):
+        hp = np.array([h[(M - 1 - m) * P + p] for m in range(M)])
+        gp = np.array([h[m * P + p] for m in range(M)])
+        ref = np.convolve(np.convolve(x[p::P], hp), gp)[:F]
+        assert np.allclose(xh[p::P], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_synthesis_taps_are_block_reversed(oracle):
+    h = np.arange(12.0)
+    assert np.array_equal(oracle.synthesis_taps(h, 4, 3), [8, 9, 10, 11, 4, 5, 6, 7, 0, 1, 2, 3])
