@@ -15,6 +15,10 @@ per-stream state between calls:
 * ``dft``     -- the DFT across branches, Z = X F (Sec. 4.1, Eq. (12)).
 * ``pfb``     -- FIR then DFT per frame (Sec. 5.2).
 * ``unfold``  -- sliding window Y(i, j) = X(i + j) (Sec. 4.4, Eq. (17)).
+* ``idft`` / ``synthesize`` -- inverse DFT (Sec. 4.2, Eq. (14)) and the
+  synthesis bank built on it.
+* ``e4m3``, ``mx_exponent``, ``mx_quantize``, ``mx_dft`` -- the block-scaled
+  FP8 form of the DFT (32-entry blocks, power-of-two scales, OCP E4M3).
 * ``Stream``  -- the filter bank on a stream fed in chunks, carrying the
   (M-1)*P history samples and the partial-frame residue between calls.
 """
@@ -67,6 +71,14 @@ def _load(path: str | None = None):
     lib.oracle_pfb.restype = i
     lib.oracle_idft.argtypes = [i64, vp, i64, vp]
     lib.oracle_idft.restype = i
+    lib.oracle_e4m3.argtypes = [d]
+    lib.oracle_e4m3.restype = d
+    lib.oracle_mx_exponent.argtypes = [d]
+    lib.oracle_mx_exponent.restype = i
+    lib.oracle_mx_quantize.argtypes = [vp, i64, vp]
+    lib.oracle_mx_quantize.restype = i
+    lib.oracle_mx_dft.argtypes = [i64, i, vp, i64, vp]
+    lib.oracle_mx_dft.restype = i
     if path is None:
         _lib = lib
     return lib
@@ -159,6 +171,36 @@ class Oracle:
         if self.lib.oracle_idft(P, self._ptr(X.view(np.float64)), X.shape[0], self._ptr(v.view(np.float64))) != 0:
             raise ValueError("oracle_idft failed")
         return v
+
+    def e4m3(self, v: float) -> float:
+        """Nearest OCP FP8 E4M3 value (ties to even, saturating at 448)."""
+        return float(self.lib.oracle_e4m3(float(v)))
+
+    def mx_exponent(self, amax: float) -> int:
+        """Smallest e in [-127, 127] with amax <= 448 * 2^e (0 for amax = 0)."""
+        return int(self.lib.oracle_mx_exponent(float(amax)))
+
+    def mx_quantize(self, v) -> np.ndarray:
+        """Block-quantised copy of a real vector (blocks of 32 entries)."""
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+        out = np.empty_like(v)
+        if self.lib.oracle_mx_quantize(self._ptr(v), v.size, self._ptr(out)) != 0:
+            raise ValueError("oracle_mx_quantize failed")
+        return out
+
+    def mx_dft(self, y) -> np.ndarray:
+        """Block-scaled FP8 DFT across branches of each row of y (frames x P,
+        real or complex); frames x K complex128 like ``dft``."""
+        y = np.asarray(y)
+        cplx = np.iscomplexobj(y)
+        P = y.shape[1]
+        yy = np.ascontiguousarray(y, dtype=np.complex128 if cplx else np.float64)
+        flat = yy.view(np.float64) if cplx else yy
+        K = P if cplx else P // 2 + 1
+        X = np.empty((y.shape[0], K), dtype=np.complex128)
+        if self.lib.oracle_mx_dft(P, int(cplx), self._ptr(flat), y.shape[0], self._ptr(X)) != 0:
+            raise ValueError("oracle_mx_dft failed")
+        return X
 
     @staticmethod
     def synthesis_taps(h, P: int, M: int) -> np.ndarray:

@@ -16,7 +16,9 @@
  *   - the DFT across branches of each frame, Z = X F with F the Fourier
  *     matrix (Sec. 4.1, Eq. (12)), forward sign, unnormalised;
  *   - the unfolding (sliding-window) operation Y(i, j) = X(i*stride + j)
- *     (Sec. 4.4, Eq. (17), stride 1 in the paper).
+ *     (Sec. 4.4, Eq. (17), stride 1 in the paper);
+ *   - the inverse DFT of Sec. 4.2, Eq. (14);
+ *   - a block-scaled FP8 form of the DFT (see oracle_mx_dft).
  *
  * Readings taken where the paper is silent:
  *   branch p of frame f holds x[f*P + p];
@@ -322,5 +324,128 @@ int oracle_pfb(int64_t P, int64_t M, int cplx, const double* h, const double* x_
         }
     }
     free(tw);
+    return failed ? -3 : 0;
+}
+
+/*
+ * Block-scaled FP8 DFT (a quantised form of the DFT of Sec. 4.1, Eq. (12);
+ * the paper names quantisation as one of the NN-side optimisations the
+ * mapping opens up, Sec. 1).  No precision is fixed by the paper; this is the
+ * definition the GPU's block-scaled form is held to:
+ *
+ *   - FP8 E4M3 (OCP): 1 sign, 4 exponent (bias 7), 3 mantissa bits; normals
+ *     2^-6 .. 448, subnormals in steps of 2^-9; rounding to nearest, ties to
+ *     even; magnitudes above 448 saturate to 448.
+ *   - Blocks: 32 consecutive entries of a real vector (the last block may be
+ *     shorter).  Each block gets one power-of-two scale 2^e, e the smallest
+ *     integer in [-127, 127] with max|v| <= 448 * 2^e (e = 0 for an all-zero
+ *     block), and each entry becomes 2^e * E4M3(v * 2^-e).
+ *   - The DFT of one frame is written as real dot products over the frame's
+ *     real vector (K = P reals, or K = 2P interleaved re, im for a complex
+ *     frame): Re X_k and Im X_k each have their own coefficient vector
+ *     (cos t / -sin t for a real frame; (cos t, sin t) and (-sin t, cos t)
+ *     per branch for a complex one, t = 2 pi pk/P).  The frame vector and
+ *     every coefficient vector are block-quantised as above, and each output
+ *     is the exact sum of the products of the quantised entries.
+ */
+double oracle_e4m3(double v) {
+    if (v != v || v == 0.0) return v;
+    double a = fabs(v);
+    if (a >= 448.0) return copysign(448.0, v);
+    int E;
+    frexp(a, &E);                   /* a = m * 2^E, m in [0.5, 1): binade 2^(E-1) */
+    int eb = E - 1;
+    if (eb < -6) eb = -6;           /* subnormals share the spacing of the lowest binade */
+    double q = ldexp(1.0, eb - 3);  /* grid spacing: 3 mantissa bits */
+    double r = nearbyint(a / q) * q;
+    if (r > 448.0) r = 448.0;
+    return copysign(r, v);
+}
+
+int oracle_mx_exponent(double amax) {
+    if (!(amax > 0.0) || isinf(amax)) return 0;
+    int e = -127;
+    while (e < 127 && ldexp(448.0, e) < amax) ++e;
+#if ORACLE_MUTATION == 9
+    if (e > -127) --e; /* planted: scale one binade too small (saturates) */
+#endif
+    return e;
+}
+
+/* Block-quantised copy of v[0..n): out[j] = 2^e * E4M3(v[j] * 2^-e). */
+int oracle_mx_quantize(const double* v, int64_t n, double* out) {
+    if (n < 0 || (n > 0 && (!v || !out))) return -1;
+    for (int64_t b = 0; b < n; b += 32) {
+        int64_t end = b + 32 < n ? b + 32 : n;
+        double amax = 0.0;
+        for (int64_t j = b; j < end; ++j)
+            if (fabs(v[j]) > amax) amax = fabs(v[j]);
+        int e = oracle_mx_exponent(amax);
+        for (int64_t j = b; j < end; ++j) out[j] = ldexp(oracle_e4m3(ldexp(v[j], -e)), e);
+    }
+    return 0;
+}
+
+int oracle_mx_dft(int64_t P, int cplx, const double* y, int64_t nframes, double* X) {
+    if (P < 2 || nframes < 0 || (nframes > 0 && (!y || !X))) return -1;
+    int cf = cplx ? 2 : 1;
+    int64_t Kin = P * cf, Kout = cplx ? P : P / 2 + 1;
+    double* tw = twiddle_table(P);
+    double* yq = (double*)malloc(sizeof(double) * (size_t)(Kin * (nframes > 0 ? nframes : 1)));
+    if (!tw || !yq) {
+        free(tw);
+        free(yq);
+        return -3;
+    }
+    for (int64_t f = 0; f < nframes; ++f) oracle_mx_quantize(y + f * Kin, Kin, yq + f * Kin);
+    int failed = 0;
+#pragma omp parallel
+    {
+        double* w = (double*)malloc(sizeof(double) * 4 * (size_t)Kin);
+        if (!w) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            double *wr = w, *wi = w + Kin, *qr = w + 2 * Kin, *qi = w + 3 * Kin;
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t k = 0; k < Kout; ++k) {
+                int64_t r = 0; /* (p * k) mod P */
+                for (int64_t p = 0; p < P; ++p) {
+                    double c = tw[2 * r], s = tw[2 * r + 1];
+                    if (cplx) {
+                        wr[2 * p] = c;
+                        wr[2 * p + 1] = s;
+                        wi[2 * p] = -s;
+                        wi[2 * p + 1] = c;
+                    } else {
+                        wr[p] = c;
+                        wi[p] = -s;
+                    }
+                    r += k;
+                    if (r >= P) r -= P;
+                }
+#if ORACLE_MUTATION == 8
+                memcpy(qr, wr, sizeof(double) * (size_t)Kin); /* planted: coefficients left unquantised */
+                memcpy(qi, wi, sizeof(double) * (size_t)Kin);
+#else
+                oracle_mx_quantize(wr, Kin, qr);
+                oracle_mx_quantize(wi, Kin, qi);
+#endif
+                for (int64_t f = 0; f < nframes; ++f) {
+                    const double* a = yq + f * Kin;
+                    double re = 0.0, im = 0.0;
+                    for (int64_t j = 0; j < Kin; ++j) {
+                        re += a[j] * qr[j];
+                        im += a[j] * qi[j];
+                    }
+                    X[(f * Kout + k) * 2] = re;
+                    X[(f * Kout + k) * 2 + 1] = im;
+                }
+            }
+            free(w);
+        }
+    }
+    free(tw);
+    free(yq);
     return failed ? -3 : 0;
 }

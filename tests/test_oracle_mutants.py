@@ -20,6 +20,8 @@ MUTANTS = {
     5: "window centred at L/2",
     6: "DFT phase index slips",
     7: "sign of the complex cross term",
+    8: "block-scaled DFT leaves the coefficients unquantised",
+    9: "block scale one binade too small (saturates)",
 }
 
 
@@ -35,6 +37,9 @@ def _run_pins(o):
         lambda: pins.test_pfb_complex_tone_closed_form(o, 16, 4, 3, "hann"),
         lambda: pins.test_pfb_equals_bank_of_bandpass_filters(o, 8, 3, 200, True),
         lambda: pins.test_pfb_equals_bank_of_bandpass_filters(o, 16, 4, 512, False),
+        lambda: pins.test_mx_exponent_is_smallest_fitting_power(o, 1.0),
+        lambda: pins.test_mx_dft_of_delta_is_the_quantised_coefficient(o, 64, False, 37),
+        lambda: pins.test_mx_dft_within_rounding_bound(o, 64, True),
     ]
     failed = []
     for i, c in enumerate(checks):

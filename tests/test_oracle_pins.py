@@ -327,3 +327,142 @@ def test_analysis_then_synthesis_is_branchwise_convolution(oracle, P, M):
 def test_synthesis_taps_are_block_reversed(oracle):
     h = np.arange(12.0)
     assert np.array_equal(oracle.synthesis_taps(h, 4, 3), [8, 9, 10, 11, 4, 5, 6, 7, 0, 1, 2, 3])
+
+
+# --------------------------------------------------------------------------
+# Block-scaled FP8 form of the DFT (quantisation, Sec. 1; DFT of Eq. (12)).
+# Pinned to torch's float8_e4m3fn cast (a library routine, round to nearest
+# even), to the format's grid, to exact cases and to a rounding-error bound.
+# --------------------------------------------------------------------------
+def _torch_e4m3(v):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
+    return t.to(torch.float8_e4m3fn).to(torch.float64).numpy()
+
+
+def _e4m3_grid():
+    import torch
+    g = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    return np.unique(g[np.isfinite(g)])
+
+
+def _block_exponent(amax):
+    # smallest e with amax <= 448 * 2^e, from the binary exponent of amax/448
+    if amax == 0.0:
+        return 0
+    m, E = np.frexp(amax / 448.0)
+    return int(E - 1) if m == 0.5 else int(E)
+
+
+def test_e4m3_matches_torch_float8(oracle):
+    g = _rng(31)
+    grid = _e4m3_grid()
+    assert grid.max() == 448.0 and grid[grid > 0].min() == 2.0 ** -9 and grid.size == 253
+    mids = (grid[1:] + grid[:-1]) / 2  # exact ties: rounding must go to the even code
+    rnd = np.concatenate([g.uniform(-448, 448, 3000),
+                          np.clip(g.standard_normal(3000) * 2.0 ** g.integers(-12, 8, 3000), -448, 448)])
+    v = np.concatenate([grid, mids, rnd.astype(np.float32).astype(np.float64)])
+    got = np.array([oracle.e4m3(x) for x in v])
+    np.testing.assert_array_equal(got, _torch_e4m3(v))
+    assert oracle.e4m3(1000.0) == 448.0 and oracle.e4m3(-1e30) == -448.0  # saturation
+
+
+@pytest.mark.parametrize("amax", [448.0, 449.0, 1.0, 0.875, 0.8749, 3e-7, 1e-40, 6.5e4, 1e38, 0.0])
+def test_mx_exponent_is_smallest_fitting_power(oracle, amax):
+    e = oracle.mx_exponent(amax)
+    assert e == max(-127, _block_exponent(amax))
+    if amax > 0:
+        assert amax <= 448.0 * 2.0 ** e
+        assert e == -127 or amax > 448.0 * 2.0 ** (e - 1)
+
+
+def test_mx_quantize_per_block(oracle):
+    g = _rng(32)
+    mags = 10.0 ** g.uniform(-4, 4, 9)
+    v = np.concatenate([g.standard_normal(32) * m for m in mags])[: 32 * 8 + 11]  # ragged last block
+    v = v.astype(np.float32).astype(np.float64)
+    q = oracle.mx_quantize(v)
+    for b in range(0, v.size, 32):
+        blk = v[b:b + 32]
+        e = _block_exponent(np.max(np.abs(blk)))
+        np.testing.assert_array_equal(q[b:b + 32], _torch_e4m3(blk * 2.0 ** -e) * 2.0 ** e)
+
+
+@pytest.mark.parametrize("P,cplx", [(4, True), (4, False), (2, False), (2, True)])
+def test_mx_dft_exact_when_everything_is_representable(oracle, P, cplx):
+    # Twiddles of P <= 4 are 0 and +-1 and small integers are E4M3 numbers at
+    # any block scale, so the quantised DFT equals the exact one.
+    g = _rng(33)
+    y = g.integers(-16, 17, (7, P)).astype(np.float64)
+    if cplx:
+        y = y + 1j * g.integers(-16, 17, (7, P))
+    ref = np.fft.fft(y, axis=1)[:, : (P if cplx else P // 2 + 1)]
+    np.testing.assert_array_equal(oracle.mx_dft(y), ref)
+
+
+@pytest.mark.parametrize("P,cplx,j", [(64, False, 37), (32, True, 21), (128, False, 0)])
+def test_mx_dft_of_delta_is_the_quantised_coefficient(oracle, P, cplx, j):
+    # y = delta at branch j: output k is coefficient j of row k, quantised with
+    # the scale of the 32-entry block that holds it.
+    y = np.zeros((1, P), dtype=np.complex128 if cplx else np.float64)
+    y[0, j] = 1.0
+    X = oracle.mx_dft(y)[0]
+    for k in range(X.size):
+        c, s = _exact_cos_sin(P, k)
+        if cplx:
+            wr = np.stack([c, s], 1).reshape(-1)
+            wi = np.stack([-s, c], 1).reshape(-1)
+            pos = 2 * j
+        else:
+            wr, wi, pos = c, -s, j
+        b = (pos // 32) * 32
+        for w, got in ((wr, X[k].real), (wi, X[k].imag)):
+            blk = w[b:b + 32]
+            e = _block_exponent(np.max(np.abs(blk)))
+            assert got == _torch_e4m3(np.array([w[pos] * 2.0 ** -e]))[0] * 2.0 ** e
+
+
+def _exact_cos_sin(P, k):
+    # cos, sin of 2 pi pk/P for p < P, with the zeros at multiples of a
+    # quarter turn exact (numpy's sin(pi) is 1.2e-16, which a block scale
+    # would otherwise blow up).
+    t = 2 * np.pi * ((np.arange(P) * k) % P) / P
+    c, s = np.cos(t), np.sin(t)
+    c[np.abs(c) < 1e-12] = 0.0
+    s[np.abs(s) < 1e-12] = 0.0
+    return c, s
+
+
+def _mx_elem_bound(v):
+    # |Q(v) - v| <= max(2^-4 |v|, 2^(e-10)) per entry (half a grid step,
+    # normal or subnormal binade), e the entry's block exponent.
+    out = np.empty_like(v)
+    for b in range(0, v.size, 32):
+        blk = v[b:b + 32]
+        e = _block_exponent(np.max(np.abs(blk)))
+        out[b:b + 32] = np.maximum(2.0 ** -4 * np.abs(blk), 2.0 ** (e - 10))
+    return out
+
+
+@pytest.mark.parametrize("P,cplx", [(128, False), (64, True)])
+def test_mx_dft_within_rounding_bound(oracle, P, cplx):
+    g = _rng(34)
+    F = 4
+    scale = np.repeat(10.0 ** g.uniform(-3, 3, (F, P * (2 if cplx else 1)) // np.array([1, 16])), 16, axis=1)
+    yr = g.standard_normal(scale.shape) * scale
+    y = yr[:, 0::2] + 1j * yr[:, 1::2] if cplx else yr
+    X = oracle.mx_dft(y)
+    ref = np.fft.fft(y, axis=1)[:, : (P if cplx else P // 2 + 1)]
+    for f in range(F):
+        a = yr[f]
+        da = _mx_elem_bound(a)
+        for k in range(X.shape[1]):
+            c, s = _exact_cos_sin(P, k)
+            if cplx:
+                rows = (np.stack([c, s], 1).reshape(-1), np.stack([-s, c], 1).reshape(-1))
+            else:
+                rows = (c, -s)
+            for w, got, exact in zip(rows, (X[f, k].real, X[f, k].imag), (ref[f, k].real, ref[f, k].imag)):
+                dw = _mx_elem_bound(w)
+                bound = np.sum(np.abs(a) * dw + da * np.abs(w) + da * dw) + 1e-9 * np.sum(np.abs(a * w))
+                assert abs(got - exact) <= bound
