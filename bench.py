@@ -25,9 +25,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp16": 2500.0, "fp16x3": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp16": 2500.0, "fp16x3": 2500.0, "fp8": 5000.0,
+               "mxfp8": 5000.0}
 PEAK_HBM_GBS = 8000.0
-MFMA_FLOP_MULT = {"fp32": 1, "bf16": 1, "fp16": 1, "bf16x3": 3, "fp16x3": 3, "fp8": 1}
+MFMA_FLOP_MULT = {"fp32": 1, "bf16": 1, "fp16": 1, "bf16x3": 3, "fp16x3": 3, "fp8": 1, "mxfp8": 1}
 
 
 def log(*a):
@@ -121,6 +122,11 @@ def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
             "dft_useful_tflops": round(flops / (dft_ms * 1e-3) / 1e12, 2),
             "dft_mfma_frac": round(flops * MFMA_FLOP_MULT[form] / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS[form], 4),
         }
+        # FIR stage bytes: FP32 input once, output FP32 (or 1 + 1/32 bytes per
+        # float in the block-scaled form, which the FIR writes directly).
+        fir_out_b = (1.0 + 1.0 / 32) if form == "mxfp8" else 4.0
+        fir_b = F * w.P * (2 if w.complex_input else 1) * (4.0 + fir_out_b)
+        res[entry]["fir_hbm_gbs"] = round(fir_b / (fir_ms * 1e-3) / 1e9, 1)
         if dft == "factored":   # the dense-DFT flop figures do not apply
             P1 = 1 << ((int(np.log2(w.P)) + 1) // 2)
             f_fact = 8.0 * w.P * (P1 + w.P // P1) * F
@@ -413,7 +419,7 @@ def main():
     if not args.no_forms:
         from oracle import Oracle
         o = Oracle()
-        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8", "fp32/factored"]
+        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8", "mxfp8", "fp32/factored"]
         result["forms"] = {w.name: forms_table(w, forms, max(5, args.steps // 2), 2, torch, o, 24)}
         del xd
         wd = workloads.wide_dynamic_range()

@@ -69,7 +69,7 @@ typedef enum tina_window {
 } tina_window;
 
 /* Arithmetic of the DFT stage (a matrix product on the MFMA units, FP32
- * accumulation).  The FIR stage is always FP32.
+ * accumulation).  The FIR stage computes in FP32 in every form.
  *   FP32       plain FP32 operands.
  *   BF16       operands rounded to bfloat16.
  *   BF16X3     operands split into bfloat16 hi + lo pieces, three products
@@ -79,14 +79,23 @@ typedef enum tina_window {
  *   FP16X3     float16 hi + lo pieces (lo scaled by 2^11), three products,
  *              same per-frame power-of-two scale.
  *   FP8_FRAME  operands in FP8 E4M3 (OCP), each frame scaled by a power of two
- *              so that its largest branch output maps to at most 448. */
+ *              so that its largest branch output maps to at most 448.
+ *   MXFP8      block-scaled FP8 (quantisation, Sec. 1): operands in E4M3 with
+ *              one power-of-two scale per 32 consecutive entries along the
+ *              summed axis (a frame's branch values, re/im interleaved for
+ *              complex input; a DFT coefficient row), the smallest with
+ *              max|v| <= 448 * scale; rounding to nearest even.  The FIR
+ *              writes this form directly (1 byte per value plus 1 per 32),
+ *              and the matrix units apply the scales.  Needs channels a
+ *              multiple of 128 (real) or 64 (complex). */
 typedef enum tina_precision {
     TINA_PREC_FP32 = 0,
     TINA_PREC_BF16 = 1,
     TINA_PREC_BF16X3 = 2,
     TINA_PREC_FP16 = 3,
     TINA_PREC_FP16X3 = 4,
-    TINA_PREC_FP8_FRAME = 5
+    TINA_PREC_FP8_FRAME = 5,
+    TINA_PREC_MXFP8 = 6
 } tina_precision;
 
 typedef enum tina_output {

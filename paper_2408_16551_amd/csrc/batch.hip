@@ -217,6 +217,12 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         fa.cf = p->cf;
         fa.amax = form_scaled(b->form) ? b->amax + amax_off : nullptr;
         fa.nparts = p->W >= 64 ? p->W / 64 : 1;  // VEC = 1 in the batched FIR
+        if (form_mx(b->form)) {  // codes, then scales, inside the item's F * W floats
+            fa.y = nullptr;
+            fa.q = (uint8_t*)(b->ws + ws_off);
+            fa.ldq = p->W;
+            fa.qs = fa.q + mx_codes_bytes(F, p->W);
+        }
         ws_off += F * p->W;
         amax_off += F * fa.nparts;
         GemmArgs& ga = bi.gemm;
@@ -233,6 +239,8 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.N = p->N;
         ga.real_pack = p->cf == 1;
         ga.form = b->form;
+        ga.Aq = fa.q;
+        ga.Aqs = fa.qs;
         bi.fir_tf = TF;
         const int64_t runs = (F + TF - 1) / TF;
         fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
@@ -299,7 +307,7 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), grid_fir, s));
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), form_mx(b->form), grid_fir, s));
     if (always || b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
@@ -424,7 +432,7 @@ tina_status tina_pfb_batch_create(int device, int precision, int max_items, int6
                                   tina_pfb_batch_t* out) {
     if (!out) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: NULL output handle");
     *out = nullptr;
-    if (precision < TINA_PREC_FP32 || precision > TINA_PREC_FP8_FRAME)
+    if (precision < TINA_PREC_FP32 || precision > TINA_PREC_MXFP8)
         return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: unknown precision");
     if (max_items < 1 || max_items > 65536) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: max_items outside [1, 65536]");
     if (workspace_bytes < (1 << 20)) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_create: workspace below 1 MiB");

@@ -1,0 +1,330 @@
+// Polyphase FIR kernels and their launch templates, shared by the
+// translation units that instantiate them (one per output mode, so that the
+// many unrolled variants compile in parallel).  Not part of the ABI.
+#pragma once
+#include "internal.h"
+
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <type_traits>
+
+namespace tina {
+
+// Output modes of the FIR: FP32 rows, FP32 rows plus per-frame partial
+// maxima (per-frame scaled forms), block-scaled FP8 codes and scales.
+enum FirOut : int { FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2 };
+
+// Launch-shape override for tuning sweeps: TINA_FIR_TUNE="vec,tf,nt"
+// (vec 0 and tf 0 keep the defaults; nt 0 turns non-temporal access off,
+// FP32-only output mode).
+struct FirTune { int vec = 0, tf = 0, nt = -1; };
+FirTune fir_tune();
+// Vector width (floats per thread) for these arguments.
+int pick_vec(const FirArgs& a);
+
+// Per-mode entry points (fir_out_*.hip).
+hipError_t launch_fir_mode_f32(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_amax(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_mx(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_batch_mode_f32(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_amax(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_mx(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+
+namespace {
+
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <int VEC> struct VecT;
+template <> struct VecT<1> { using T = float; };
+template <> struct VecT<2> { using T = fvec2; };
+template <> struct VecT<4> { using T = fvec4; };
+
+template <int VEC>
+__device__ inline float vget(const typename VecT<VEC>::T& v, int i) {
+    if constexpr (VEC == 1) return v;
+    else return v[i];
+}
+template <int VEC>
+__device__ inline void vset(typename VecT<VEC>::T& v, int i, float x) {
+    if constexpr (VEC == 1) v = x;
+    else v[i] = x;
+}
+
+template <bool NTL, class V>
+__device__ inline V ld(const V* p) {
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NTS, class V>
+__device__ inline void st(V* p, const V& v) {
+    if constexpr (NTS) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+__device__ __attribute__((aligned(16))) float kZeros[4] = {0.f, 0.f, 0.f, 0.f};
+
+// Input floats j0..j0+VEC-1 of frame g (g >= -(M-1)); ext = prefix ++ chunk,
+// frame g starting at ext float (g + M - 1) * W.  The VEC floats never
+// straddle the prefix/chunk boundary (plen is a multiple of VEC).  The source
+// is chosen by a pointer select, not a branch, so that the loads of a block of
+// frames can all be in flight together.
+template <int VEC, bool NTL>
+__device__ inline typename VecT<VEC>::T load_frame(const FirArgs& a, int64_t g, int j0) {
+    using V = typename VecT<VEC>::T;
+    const int64_t e = (g + a.M - 1) * (int64_t)a.W + j0;
+    const float* hist = a.prefix ? a.prefix + e : kZeros;
+    const float* p = e >= a.plen ? a.chunk + (e - a.plen) : hist;
+    return ld<NTL>(reinterpret_cast<const V*>(p));
+}
+
+// Taps of the VEC columns j0.. for tap m: h[(M-1-m)*P + (j0+v)/cf].
+template <int VEC>
+__device__ inline typename VecT<VEC>::T load_taps(const FirArgs& a, int M, int m, int j0) {
+    using V = typename VecT<VEC>::T;
+    const float* base = a.taps + (int64_t)(M - 1 - m) * a.P;
+    if (a.cf == 1) return *reinterpret_cast<const V*>(base + j0);
+    V t;
+    if constexpr (VEC == 4) {
+        const fvec2 v = *reinterpret_cast<const fvec2*>(base + (j0 >> 1));
+        t[0] = v[0]; t[1] = v[0]; t[2] = v[1]; t[3] = v[1];
+    } else if constexpr (VEC == 2) {
+        const float v = base[j0 >> 1];
+        t[0] = v; t[1] = v;
+    } else {
+        t = base[j0 >> 1];
+    }
+    return t;
+}
+
+// One output frame from ring slot u (the newest frame) and the MT-1 before it.
+template <int VEC, int MT, bool EXACT>
+__device__ __forceinline__ typename VecT<VEC>::T fir_point(const typename VecT<VEC>::T (&tp)[MT],
+                                                           const typename VecT<VEC>::T (&win)[MT], int u, int M) {
+    typename VecT<VEC>::T acc = tp[0] * win[u];
+#pragma unroll
+    for (int m = 1; m < MT; ++m) {
+        if (EXACT || m < M) acc = __builtin_elementwise_fma(tp[m], win[(u - m + MT) % MT], acc);
+    }
+    return acc;
+}
+
+template <int VEC, bool AMAX>
+__device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
+                                         int gw) {
+    if constexpr (AMAX) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
+        for (int off = gw >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, gw));
+        if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
+    }
+}
+
+// Smallest e in [-127, 127] with amax <= 448 * 2^e (0 for a zero or
+// non-finite amax): the block scale of the block-scaled FP8 output.
+__device__ inline int mx_exponent(float amax) {
+    if (!(amax > 0.0f) || !isfinite(amax)) return 0;
+    int e;
+    frexpf(amax / 448.0f, &e);  // a first guess, then exact comparisons
+    e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    while (e > -127 && ldexpf(448.0f, e - 1) >= amax) --e;
+    while (e < 127 && ldexpf(448.0f, e) < amax) ++e;
+    return e;
+}
+
+// Store one output vector: FP32 (plus the frame's partial maximum when AMAX),
+// or, when QOUT, block-scaled FP8: the 32/VEC lanes that hold one 32-float
+// block of the frame share its maximum through a butterfly, every lane writes
+// the E4M3 codes of its VEC floats scaled by 2^-e, and the block's first lane
+// writes the E8M0 scale byte e + 127.
+template <int VEC, bool AMAX, bool QOUT, bool NT>
+__device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
+                                          int gw, int j0) {
+    using V = typename VecT<VEC>::T;
+    if constexpr (QOUT) {
+        constexpr int GL = 32 / VEC;  // lanes per 32-float block
+        float mx = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
+#pragma unroll
+        for (int off = GL >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        const int e = mx_exponent(mx);
+        const float sc = ldexpf(1.0f, -e);
+        float x[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) x[v] = fminf(fmaxf(vget<VEC>(acc, v) * sc, -448.0f), 448.0f);
+        uint8_t* dst = a.q + f * a.ldq + j0;
+        if constexpr (VEC == 4) {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
+            st<NT>(reinterpret_cast<int*>(dst), w);
+        } else if constexpr (VEC == 2) {
+            const int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+            st<NT>(reinterpret_cast<uint16_t*>(dst), (uint16_t)w);
+        } else {
+            const int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false);
+            st<NT>(dst, (uint8_t)w);
+        }
+        if ((col & (GL - 1)) == 0) a.qs[f * (a.W / 32) + j0 / 32] = (uint8_t)(e + 127);
+    } else {
+        st<NT>(reinterpret_cast<V*>(a.y + f * a.ldy + j0), acc);
+        fir_amax<VEC, AMAX>(a, acc, f, col, gw);
+    }
+}
+
+// MT: ring length (unroll); EXACT: M == MT (no per-tap predicate);
+// NT: non-temporal input loads and output stores (streaming cache policy);
+// QOUT: block-scaled FP8 output (a.q, a.qs) instead of FP32 (a.y).
+// One 256-thread unit of work: logical block `blk` of the (column, run) grid.
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, bool QOUT = false>
+__device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) {
+    using V = typename VecT<VEC>::T;
+    const int ct = a.W / VEC;                    // threads per frame row (power of two)
+    const int64_t gid = blk * 256 + threadIdx.x;
+    const int col = (int)(gid & (ct - 1));
+    const int64_t run = gid / ct;
+    const int64_t f_begin = run * TF;
+    if (f_begin >= a.F) return;                  // whole groups of `ct` lanes leave together
+    const int64_t f_end = min(a.F, f_begin + TF);
+    const int j0 = col * VEC;
+    const int M = EXACT ? MT : a.M;
+    const int gw = ct < 64 ? ct : 64;            // lanes sharing one frame row in a wave
+
+    V tp[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) tp[m] = (EXACT || m < M) ? load_taps<VEC>(a, M, m, j0) : V(0.0f);
+
+    V win[MT];
+    // Frames f_begin - d (d = 1..M-1) go to ring slot MT - d (f_begin is a multiple of MT).
+#pragma unroll
+    for (int d = 1; d < MT; ++d) {
+        win[MT - d] = (EXACT || d < M) ? load_frame<VEC, false>(a, a.g0 + f_begin - d, j0) : V(0.0f);
+    }
+    win[0] = V(0.0f);
+
+    // Full blocks of MT frames, loaded SB frames at a time: the SB loads of a
+    // sub-block issue before its first FMA.
+    constexpr int SB = (VEC == 4 ? 8 : 16) < MT ? (VEC == 4 ? 8 : 16) : MT;
+    int64_t fb = f_begin;
+    for (; fb + MT <= f_end; fb += MT) {
+#pragma unroll
+        for (int sb = 0; sb < MT; sb += SB) {
+            V in[SB];
+#pragma unroll
+            for (int i = 0; i < SB; ++i) in[i] = load_frame<VEC, NT>(a, a.g0 + fb + sb + i, j0);
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                const int u = sb + i;
+                win[u] = in[i];
+                const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
+                fir_store<VEC, AMAX, QOUT, NT>(a, acc, fb + u, col, gw, j0);
+            }
+        }
+    }
+    // Tail block.
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+        if (fb + u < f_end) {
+            win[u] = load_frame<VEC, NT>(a, a.g0 + fb + u, j0);
+            const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
+            fir_store<VEC, AMAX, QOUT, NT>(a, acc, fb + u, col, gw, j0);
+        }
+    }
+}
+
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, bool QOUT>
+__global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
+    fir_unit<VEC, MT, EXACT, AMAX, NT, QOUT>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// Persistent batched FIR: each block walks its XCD's contiguous, cost-balanced
+// range of units (see BatchTable); a unit is one 256-thread block of one item.
+template <int MT, bool EXACT, bool AMAX, bool QOUT>
+__global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __restrict__ t) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t end = t->fir_bounds[x + 1];
+    for (int64_t u = t->fir_bounds[x] + i; u < end; u += nbx) {
+        const int it = batch_find(t->items, t->n_items, u, /*stage=*/0);
+        const BatchItem& b = t->items[it];
+        fir_unit<1, MT, EXACT, AMAX, true, QOUT>(b.fir, b.fir_tf, u - b.fir_unit0);
+    }
+}
+
+template <int VEC, int MT, bool EXACT, int MODE>
+hipError_t launch_one(FirArgs& a, hipStream_t s) {
+    constexpr bool AMAX = MODE == FIR_OUT_AMAX, QOUT = MODE == FIR_OUT_MX;
+    const int ct = a.W / VEC;
+    // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
+    // least 16) keeps the halo re-reads in L2 while leaving enough waves to
+    // hide HBM latency.
+    int TF = 2 * MT < 16 ? 16 : 2 * MT;
+    const FirTune tune = fir_tune();
+    if (tune.tf > 0) TF = ((tune.tf + MT - 1) / MT) * MT;
+    const int64_t runs = (a.F + TF - 1) / TF;
+    const int64_t threads = runs * ct;
+    const int64_t blocks = (threads + 255) / 256;
+    // Non-temporal loads and stores (streaming data, measured faster); the
+    // FP32 mode can turn them off for tuning sweeps.
+    if constexpr (MODE == FIR_OUT_F32) {
+        if (tune.nt == 0) {
+            hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, false, false, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               a, TF);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, true, QOUT>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
+    return hipGetLastError();
+}
+
+template <int VEC, int MT, int MODE>
+hipError_t launch_mt(FirArgs& a, hipStream_t s) {
+    return a.M == MT ? launch_one<VEC, MT, true, MODE>(a, s) : launch_one<VEC, MT, false, MODE>(a, s);
+}
+
+template <int VEC, int MODE>
+hipError_t launch_vec(FirArgs& a, hipStream_t s) {
+    if (a.M <= 1) return launch_mt<VEC, 1, MODE>(a, s);
+    if (a.M <= 2) return launch_mt<VEC, 2, MODE>(a, s);
+    if (a.M <= 4) return launch_mt<VEC, 4, MODE>(a, s);
+    if (a.M <= 8) return launch_mt<VEC, 8, MODE>(a, s);
+    if (a.M <= 16) return launch_mt<VEC, 16, MODE>(a, s);
+    if constexpr (VEC <= 2) {
+        if (a.M <= 32) return launch_mt<VEC, 32, MODE>(a, s);
+    }
+    if constexpr (VEC == 1) {
+        if (a.M <= 64) return launch_mt<VEC, 64, MODE>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MODE>
+hipError_t launch_mode(FirArgs& a, int vec, hipStream_t s) {
+    switch (vec) {
+        case 4: return launch_vec<4, MODE>(a, s);
+        case 2: return launch_vec<2, MODE>(a, s);
+        default: return launch_vec<1, MODE>(a, s);
+    }
+}
+
+template <int MODE>
+hipError_t launch_batch_mode(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
+    constexpr bool AMAX = MODE == FIR_OUT_AMAX, QOUT = MODE == FIR_OUT_MX;
+    auto go = [&](auto mt_tag) -> hipError_t {
+        constexpr int MT = decltype(mt_tag)::value;
+        if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, AMAX, QOUT>), dim3(grid), dim3(256), 0, s, t);
+        else hipLaunchKernelGGL((fir_batch_kernel<MT, false, AMAX, QOUT>), dim3(grid), dim3(256), 0, s, t);
+        return hipGetLastError();
+    };
+    if (max_m <= 1) return go(std::integral_constant<int, 1>{});
+    if (max_m <= 2) return go(std::integral_constant<int, 2>{});
+    if (max_m <= 4) return go(std::integral_constant<int, 4>{});
+    if (max_m <= 8) return go(std::integral_constant<int, 8>{});
+    if (max_m <= 16) return go(std::integral_constant<int, 16>{});
+    if (max_m <= 32) return go(std::integral_constant<int, 32>{});
+    if (max_m <= 64) return go(std::integral_constant<int, 64>{});
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+}  // namespace tina

@@ -27,13 +27,17 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
+// EB: operand bytes per element in LDS; NP: pieces per operand; SLAB: bytes
+// of a row consumed by one MFMA; SCALED: per-frame scale; MX: A arrives as
+// block-scaled FP8 (codes + one scale byte per 32 K), B likewise.
 template <int FORM> struct FT;
-template <> struct FT<FORM_FP32> { static constexpr int EB = 4, NP = 1, SLAB = 32; static constexpr bool SCALED = false; };
-template <> struct FT<FORM_BF16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = false; };
-template <> struct FT<FORM_BF16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = false; };
-template <> struct FT<FORM_FP16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = true; };
-template <> struct FT<FORM_FP16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = true; };
-template <> struct FT<FORM_FP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = true; };
+template <> struct FT<FORM_FP32> { static constexpr int EB = 4, NP = 1, SLAB = 32; static constexpr bool SCALED = false, MX = false; };
+template <> struct FT<FORM_BF16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = false, MX = false; };
+template <> struct FT<FORM_BF16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = false, MX = false; };
+template <> struct FT<FORM_FP16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
+template <> struct FT<FORM_FP16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
+template <> struct FT<FORM_FP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = true, MX = false; };
+template <> struct FT<FORM_MXFP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = false, MX = true; };
 
 constexpr int BM = 128, BN = 128;     // block tile
 constexpr int ROWB = 128;             // bytes of each operand row per K tile
@@ -64,9 +68,12 @@ __device__ inline float f16_round(float a) { return (float)(_Float16)a; }
 // term-major (every block's hi*hi, then every block's hi*lo, ...), so MFMAs
 // that accumulate into the same registers are four instructions apart.
 // af[bm][piece][read], bf[bn][piece][read]: the lane's 16-byte K slices.
+// sa/sb (block-scaled form): the lane's E8M0 scale in the low byte, one per
+// 32-K block of the lane's row / column.
 template <int FORM, int NP, int RD>
 __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[2][NP][RD],
-                                          f32x16 (&acc)[2][2], f32x16 (&acc2)[2][2]) {
+                                          f32x16 (&acc)[2][2], f32x16 (&acc2)[2][2], const int (&sa)[2],
+                                          const int (&sb)[2]) {
     if constexpr (FORM == FORM_FP32) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -120,9 +127,14 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
                 av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
                 bv[0] = b0.x; bv[1] = b0.y; bv[2] = b0.z; bv[3] = b0.w;
                 bv[4] = b1.x; bv[5] = b1.y; bv[6] = b1.z; bv[7] = b1.w;
-                // Formats 0/0 = FP8 E4M3 for both operands; block scales 2^0 (E8M0 127).
-                acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[bm][bn], 0, 0, 0, 0x7f7f7f7f,
-                                                                              0, 0x7f7f7f7f);
+                // Formats 0/0 = FP8 E4M3 for both operands.  Per-frame form:
+                // block scales 2^0 (E8M0 127); block-scaled form: the lane's own.
+                if constexpr (FORM == FORM_MXFP8)
+                    acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[bm][bn], 0, 0, 0, sa[bm],
+                                                                                  0, sb[bn]);
+                else
+                    acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[bm][bn], 0, 0, 0,
+                                                                                  0x7f7f7f7f, 0, 0x7f7f7f7f);
             }
     }
 }
@@ -132,6 +144,7 @@ struct GemmSmem {
     static constexpr int NP = FT<FORM>::NP;
     uint8_t tiles[2 * NP * BM * RS];  // NP A pieces then NP B pieces, BM (= BN) rows of RS bytes
     float inv[BM], sc[BM];            // per-frame scale and its inverse
+    uint32_t mxs[FT<FORM>::MX ? BM + BN : 1];  // block scales of the K tile: 4 bytes per A row, then B row
 };
 
 // Map a logical tile index L of an nm x nn grid: groups of GROUP_M m-tiles
@@ -152,7 +165,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
     constexpr int BK = ROWB / EB;                 // K elements per tile
     constexpr int ACPR = BK / 4;                  // A float4 chunks per row
-    constexpr int ACH = BM * ACPR / NT;           // A chunks per thread
+    constexpr int ACH = ft::MX ? 1 : BM * ACPR / NT;  // A float4 chunks per thread (FP32 A)
     constexpr int BCH = BN * (ROWB / 16) / NT;    // B 16-byte chunks per thread per piece
     constexpr int NSLAB = ROWB / SLAB;
     constexpr int RD = SLAB / 32;                 // 16-byte reads per lane per slab
@@ -181,12 +194,42 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         __syncthreads();
     }
 
+    static_assert(!ft::MX || (BM + BN == NT && NP == 1), "block-scaled form: one scale word per thread");
     float4 ra[ACH];
     uint4 rb[NP][BCH];
+    uint4 rqa[ft::MX ? BCH : 1];  // block-scaled form: A codes
+    uint32_t rsc = 0;             // block-scaled form: this thread's scale word
     const uint8_t* Bp[2] = {(const uint8_t*)g.B0, (const uint8_t*)g.B1};
     const int64_t KB = (int64_t)g.K * EB;  // bytes per Bt row
 
     auto load_tile = [&](int k0) {
+        if constexpr (ft::MX) {
+            // K % 128 == 0 (checked at plan time): every K tile is whole.
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int64_t f = m0 + row;
+                rqa[i] = f < g.F ? *reinterpret_cast<const uint4*>(g.Aq + f * g.lda + k0 + kc * 16)
+                                 : make_uint4(0u, 0u, 0u, 0u);
+            }
+            const int64_t nb = g.K / 32;
+            if (tid < BM) {
+                const int64_t f = m0 + tid;
+                rsc = f < g.F ? *reinterpret_cast<const uint32_t*>(g.Aqs + f * nb + k0 / 32) : 0x7f7f7f7fu;
+            } else {
+                const int64_t n = n0 + tid - BM;
+                rsc = n < g.N ? *reinterpret_cast<const uint32_t*>((const uint8_t*)g.B1 + n * nb + k0 / 32)
+                              : 0x7f7f7f7fu;
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int64_t n = n0 + row;
+                rb[0][i] = n < g.N ? *reinterpret_cast<const uint4*>(Bp[0] + n * KB + (int64_t)k0 + kc * 16)
+                                   : make_uint4(0u, 0u, 0u, 0u);
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) {
             const int c = tid + i * NT, row = c / ACPR, kc = c % ACPR;
@@ -208,6 +251,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     };
 
     auto store_tile = [&]() {
+        if constexpr (ft::MX) {
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                *reinterpret_cast<uint4*>(As + row * RS + kc * 16) = rqa[i];
+                *reinterpret_cast<uint4*>(Bs + row * RS + kc * 16) = rb[0][i];
+            }
+            sm.mxs[tid] = rsc;
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) {
             const int c = tid + i * NT, row = c / ACPR, kc = c % ACPR;
@@ -266,6 +319,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
         for (int s = 0; s < NSLAB; ++s) {
             uint4 af[2][NP][RD], bf[2][NP][RD];
+            // The lane's 16-byte reads of the slab.  For the 64-K FP8 MFMA
+            // this puts the instruction's K index equal to the byte offset in
+            // the slab (bytes 0-15 of lane half lh are K 16 lh.., bytes 16-31
+            // are K 32 + 16 lh..), so its 32-K scale block b is bytes
+            // [32 b, 32 b + 32) of the slab, whose scale lane half b supplies.
+            auto off = [&](int q) { return s * SLAB + q * 32 + lh * 16; };
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -273,7 +332,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
                     for (int q = 0; q < RD; ++q) {
                         const int row = wm * 64 + bm * 32 + lr;
-                        af[bm][p][q] = *reinterpret_cast<const uint4*>(As + p * BM * RS + row * RS + s * SLAB + q * 32 + lh * 16);
+                        af[bm][p][q] = *reinterpret_cast<const uint4*>(As + p * BM * RS + row * RS + off(q));
                     }
 #pragma unroll
             for (int bn = 0; bn < 2; ++bn)
@@ -282,9 +341,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
                     for (int q = 0; q < RD; ++q) {
                         const int row = wn * 64 + bn * 32 + lr;
-                        bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + s * SLAB + q * 32 + lh * 16);
+                        bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + off(q));
                     }
-            mfma_slab<FORM, NP, RD>(af, bf, acc, acc2);
+            int sa[2] = {0, 0}, sb[2] = {0, 0};
+            if constexpr (ft::MX) {
+                const int sh = 8 * (2 * s + lh);  // byte of the word = 32-K block of the K tile
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    sa[b] = (int)(sm.mxs[wm * 64 + b * 32 + lr] >> sh);
+                    sb[b] = (int)(sm.mxs[BM + wn * 64 + b * 32 + lr] >> sh);
+                }
+            }
+            mfma_slab<FORM, NP, RD>(af, bf, acc, acc2, sa, sb);
         }
         __syncthreads();
         if (t + 1 < nk) {
@@ -363,6 +431,7 @@ hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_
         case FORM_FP16: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16>, dim3(grid), dim3(NT), 0, s, t); break;
         case FORM_FP16X3: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16X3>, dim3(grid), dim3(NT), 0, s, t); break;
         case FORM_FP8: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP8>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_MXFP8: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_MXFP8>, dim3(grid), dim3(NT), 0, s, t); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -377,6 +446,7 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
         case FORM_FP16: return launch_form<FORM_FP16>(g, s);
         case FORM_FP16X3: return launch_form<FORM_FP16X3>(g, s);
         case FORM_FP8: return launch_form<FORM_FP8>(g, s);
+        case FORM_MXFP8: return (g.K % 128 == 0) ? launch_form<FORM_MXFP8>(g, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -131,6 +131,30 @@ __global__ void dft_operand_kernel(void* piece0, void* piece1, int P, int cplx, 
     }
 }
 
+// Block-scaled FP8 operand: thread t handles row n = t / (K/32), block b =
+// t % (K/32) of Bt: the 32 FP64 entries, the smallest power-of-two scale 2^e
+// (e in [-127, 127]) with max|v| <= 448 * 2^e, E4M3 codes of v * 2^-e
+// (round to nearest even) and the E8M0 scale byte e + 127.
+__global__ void mx_operand_kernel(uint8_t* codes, uint8_t* scales, int P, int cplx) {
+    const int64_t N = cplx ? 2 * (int64_t)P : P;
+    const int64_t K = N, nb = K / 32;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nb) return;
+    const int64_t n = t / nb, k0 = (t % nb) * 32;
+    double v[32], amax = 0.0;
+    for (int i = 0; i < 32; ++i) {
+        v[i] = dft_entry(n, k0 + i, P, cplx, 0);
+        amax = fmax(amax, fabs(v[i]));
+    }
+    int e = 0;
+    if (amax > 0.0) {
+        e = -127;
+        while (e < 127 && ldexp(448.0, e) < amax) ++e;
+    }
+    for (int i = 0; i < 32; ++i) codes[n * K + k0 + i] = e4m3_bits_exact(round_sig(ldexp(v[i], -e), 4, -6));
+    scales[t] = (uint8_t)(e + 127);
+}
+
 // Block-reversed FP32 taps of the synthesis FIR: g'[(M-1-m) P + p] = h[m P + p].
 __global__ void synthesis_taps_kernel(const double* h64, float* g32, int P, int M) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,6 +187,13 @@ hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int cplx, int f
     const int64_t N = cplx ? 2 * (int64_t)P : P;
     const int64_t total = N * N;
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (form == FORM_MXFP8) {
+        if (inverse || N % 32 != 0) return hipErrorInvalidValue;
+        const int64_t blocks = N * (N / 32);
+        hipLaunchKernelGGL(mx_operand_kernel, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s, (uint8_t*)piece0,
+                           (uint8_t*)piece1, P, cplx);
+        return hipGetLastError();
+    }
     switch (form) {
         case FORM_FP32: hipLaunchKernelGGL(dft_operand_kernel<FORM_FP32>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;
         case FORM_BF16: hipLaunchKernelGGL(dft_operand_kernel<FORM_BF16>, grid, block, 0, s, piece0, piece1, P, cplx, inverse); break;

@@ -7,11 +7,21 @@
 namespace tina {
 
 // Arithmetic forms of the DFT stage (same values as tina_precision).
-enum Form : int { FORM_FP32 = 0, FORM_BF16 = 1, FORM_BF16X3 = 2, FORM_FP16 = 3, FORM_FP16X3 = 4, FORM_FP8 = 5 };
+enum Form : int {
+    FORM_FP32 = 0, FORM_BF16 = 1, FORM_BF16X3 = 2, FORM_FP16 = 3, FORM_FP16X3 = 4, FORM_FP8 = 5, FORM_MXFP8 = 6
+};
 
+// Forms with a per-frame scale (the FIR also writes per-frame partial maxima).
 inline bool form_scaled(int f) { return f == FORM_FP16 || f == FORM_FP16X3 || f == FORM_FP8; }
+// Block-scaled FP8: the FIR writes E4M3 codes plus one E8M0 scale per 32
+// floats of a frame, and the GEMM reads them as they are.
+inline bool form_mx(int f) { return f == FORM_MXFP8; }
 inline int form_pieces(int f) { return (f == FORM_BF16X3 || f == FORM_FP16X3) ? 2 : 1; }
-inline int form_elem_bytes(int f) { return f == FORM_FP32 ? 4 : (f == FORM_FP8 ? 1 : 2); }
+inline int form_elem_bytes(int f) { return f == FORM_FP32 ? 4 : ((f == FORM_FP8 || f == FORM_MXFP8) ? 1 : 2); }
+// Bytes of one block-scaled FP8 matrix of `rows` x `k` entries: codes, then
+// one scale byte per 32 entries of each row.
+inline int64_t mx_codes_bytes(int64_t rows, int64_t k) { return rows * k; }
+inline int64_t mx_bytes(int64_t rows, int64_t k) { return rows * k + rows * (k / 32); }
 
 // Map a hardware block index to a logical tile index so that the blocks the
 // dispatcher places on one XCD (it deals blocks round-robin over the 8 XCDs)
@@ -29,6 +39,7 @@ hipError_t launch_window(double* h64, float* h32, int P, int M, int window, hipS
 hipError_t launch_taps_to_f32(const double* h64, float* h32, int64_t L, hipStream_t s);
 // DFT operand Bt[N][K] (row n = output column, K contiguous) in the pieces of
 // `form`: piece0 (and piece1 for split forms), element size form_elem_bytes.
+// FORM_MXFP8: piece0 = E4M3 codes [N][K], piece1 = E8M0 scales [N][K/32].
 hipError_t launch_dft_operand(void* piece0, void* piece1, int P, int complex_input, int form,
                               hipStream_t s, int inverse = 0);
 // Block-reversed FP32 taps of the synthesis FIR.
@@ -49,6 +60,9 @@ struct FirArgs {
     int32_t P, M, cf;     // channels, taps, floats per sample
     float* amax;          // optional per-frame partial |y| maxima [F][nparts]
     int32_t nparts;       // filled in by launch_fir
+    uint8_t* q;           // block-scaled FP8 output instead of y (nullptr: FP32 y):
+    int64_t ldq;          //   E4M3 codes [F][ldq bytes] and
+    uint8_t* qs;          //   E8M0 scales [F][W/32] (one per 32 floats of a frame)
 };
 // Chooses the vector width and unroll; returns the number of partial maxima
 // per frame through a.nparts when a.amax is set.
@@ -74,6 +88,8 @@ struct GemmArgs {
     int32_t K, N;
     int32_t real_pack;     // real input: column 0 -> X_0, column 1 -> X_{P/2}, rest in place
     int32_t form;
+    const uint8_t* Aq;     // FORM_MXFP8: A as E4M3 codes [F][lda bytes] ...
+    const uint8_t* Aqs;    //   ... and E8M0 scales [F][K/32]; B0/B1 = Bt codes / scales
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
 
@@ -135,7 +151,8 @@ __device__ inline int batch_find(const BatchItem* items, int n, int64_t u, int s
 // GEMM tile geometry shared with the batch planner.
 constexpr int kGemmBM = 128, kGemmBN = 128;
 
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int grid, hipStream_t s);
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, bool qout, int grid,
+                             hipStream_t s);
 hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s);
 

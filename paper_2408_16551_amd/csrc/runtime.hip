@@ -51,7 +51,7 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown window");
     if (d->output != TINA_OUT_PFB && d->output != TINA_OUT_FIR_ONLY && d->output != TINA_OUT_INVERSE)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown output");
-    if (d->output != TINA_OUT_FIR_ONLY && (d->precision < TINA_PREC_FP32 || d->precision > TINA_PREC_FP8_FRAME))
+    if (d->output != TINA_OUT_FIR_ONLY && (d->precision < TINA_PREC_FP32 || d->precision > TINA_PREC_MXFP8))
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown precision");
     if (d->window == TINA_WINDOW_CUSTOM && !d->custom_taps)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: CUSTOM window without custom_taps");
@@ -63,6 +63,9 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         (d->sample_type != TINA_SAMPLE_C64 || dft_alg != TINA_DFT_DENSE ||
          !(d->precision == TINA_PREC_FP32 || d->precision == TINA_PREC_BF16 || d->precision == TINA_PREC_BF16X3)))
         return fail(TINA_ERR_UNSUPPORTED, "plan: the synthesis bank needs complex64, the dense DFT and FP32, BF16 or BF16X3");
+    if (d->output == TINA_OUT_PFB && d->precision == TINA_PREC_MXFP8 &&
+        (int64_t)d->channels * (d->sample_type == TINA_SAMPLE_C64 ? 2 : 1) % 128 != 0)
+        return fail(TINA_ERR_UNSUPPORTED, "plan: MXFP8 needs 128 | channels (real) or 64 | channels (complex)");
     if (dft_alg == TINA_DFT_FACTORED && d->output == TINA_OUT_PFB &&
         (d->precision != TINA_PREC_FP32 || !fft_supported(d->channels)))
         return fail(TINA_ERR_UNSUPPORTED, "plan: the factored DFT needs FP32 and 256 <= channels <= 4096");
@@ -131,6 +134,11 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
                 hipMalloc(&p->fft_tw, sizeof(float) * 2 * p->P) != hipSuccess)
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: factored DFT tables");
             e = launch_fft_tables(p->fft_mat1, p->fft_mat3, p->fft_tw, p->P, nullptr);
+        } else if (form_mx(form)) {
+            if (hipMalloc(&p->B[0], mx_codes_bytes(p->N, p->K)) != hipSuccess ||
+                hipMalloc(&p->B[1], (int64_t)p->N * (p->K / 32)) != hipSuccess)
+                return bail(TINA_ERR_OUT_OF_MEMORY, "plan: DFT operand allocation");
+            e = launch_dft_operand(p->B[0], p->B[1], p->P, p->cf == 2, form, nullptr);
         } else {
             const int64_t nbytes = (int64_t)p->N * p->K * form_elem_bytes(form);
             for (int i = 0; i < form_pieces(form); ++i)
@@ -253,6 +261,12 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.g0 = c0;
             fa.F = Fc;
             fa.amax = form_scaled(form) ? p->amax : nullptr;
+            if (form_mx(form)) {  // codes, then scales, in the FP32 workspace (4 bytes per float)
+                fa.y = nullptr;
+                fa.q = (uint8_t*)p->ws;
+                fa.ldq = p->W;
+                fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
+            }
             HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
             if (p->dft_algorithm == TINA_DFT_FACTORED) {
                 FftArgs xa{};
@@ -284,6 +298,8 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             ga.N = p->N;
             ga.real_pack = p->cf == 1;
             ga.form = form;
+            ga.Aq = fa.q;
+            ga.Aqs = fa.qs;
             HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
     }

@@ -308,7 +308,7 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     if (!c || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: NULL argument");
     *out = nullptr;
     if (c->struct_size < sizeof(tina_server_config)) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: struct_size too small");
-    if (c->precision < TINA_PREC_FP32 || c->precision > TINA_PREC_FP8_FRAME)
+    if (c->precision < TINA_PREC_FP32 || c->precision > TINA_PREC_MXFP8)
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: unknown precision");
     if (c->max_streams < 1 || c->max_active < 1 || c->max_queued < 1 || c->frames_per_step < 1 ||
         c->hbm_budget_bytes < 4096)

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libtina_pfb.so")
 
 SAMPLE = {"r32": 0, "c64": 1}
 WINDOW = {"rect": 0, "hann": 1, "hamming": 2, "blackman": 3, "custom": 4}
-PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5}
+PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5, "mxfp8": 6}
 OUTPUT = {"pfb": 0, "fir": 1, "inverse": 2}
 
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 
 FP32_BOUND = 1e-5
 # Relative-L2 bounds of the reduced forms vs the FP64 oracle.
-REDUCED_BOUNDS = {"bf16": 8e-3, "bf16x3": 2e-5, "fp16": 1e-3, "fp16x3": 1e-6, "fp8": 0.1}
+REDUCED_BOUNDS = {"bf16": 8e-3, "bf16x3": 2e-5, "fp16": 1e-3, "fp16x3": 1e-6, "fp8": 0.1, "mxfp8": 0.05}
 
 
 def rel_l2(got, ref):
@@ -260,7 +260,7 @@ def test_full_size_real_stream_fp32_sampled(oracle, real_stream_wl):
     assert rel_l2(got, ref) < FP32_BOUND
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "fp8", "mxfp8"])
 def test_full_size_wide_dynamic_range_sampled(oracle, precision, wide_wl):
     w = wide_wl
     plan = _plan(w.P, w.M, True, window=w.window, precision=precision)
