@@ -34,10 +34,16 @@ int pick_vec(const FirArgs& a) {
     // Vector width by register budget (taps, ring and prefetch each take
     // MT*VEC registers): 4 floats for up to 8 taps, else 1 (measured best).
     int vec = a.M <= 8 ? 4 : 1;
+    // Block-scaled output: 4 floats per thread up to 16 taps (the per-block
+    // maximum is then shared among 8 lanes, and a lane's 4 codes leave in one
+    // store; measured faster than 1 or 2 at 16 taps).
+    if (a.q && a.M <= 16) vec = 4;
     const FirTune tune = fir_tune();
-    if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec < vec ? tune.vec : vec;
+    if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec;
+    if (vec == 4 && a.M > 16) vec = 2;  // widest ring per vector width: 16 taps (VEC 4), 32 (VEC 2), 64 (VEC 1)
+    if (vec == 2 && a.M > 32) vec = 1;
     auto out_ok = [&](int v) {
-        if (a.q) return aligned(a.q, v) && a.ldq % v == 0;
+        if (a.q) return aligned(a.q, 4) && a.ldq % 4 == 0;  // codes leave in 4-byte stores
         return aligned(a.y, 4 * v) && a.ldy % v == 0;
     };
     while (vec > 1 && !(a.plen % vec == 0 && aligned(a.chunk, 4 * vec) && out_ok(vec) &&

@@ -16,8 +16,9 @@ namespace tina {
 enum FirOut : int { FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2 };
 
 // Launch-shape override for tuning sweeps: TINA_FIR_TUNE="vec,tf,nt"
-// (vec 0 and tf 0 keep the defaults; nt 0 turns non-temporal access off,
-// FP32-only output mode).
+// (vec 0 and tf 0 keep the defaults, vec 1/2/4 forces the vector width where
+// the register ring allows it; nt 0 turns non-temporal access off, FP32
+// output mode only).
 struct FirTune { int vec = 0, tf = 0, nt = -1; };
 FirTune fir_tune();
 // Vector width (floats per thread) for these arguments.
@@ -122,53 +123,142 @@ __device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<V
 }
 
 // Smallest e in [-127, 127] with amax <= 448 * 2^e (0 for a zero or
-// non-finite amax): the block scale of the block-scaled FP8 output.
+// non-finite amax): the block scale of the block-scaled FP8 output.  With
+// amax = m 2^E, m in [0.5, 1), and 448 = 0.875 * 2^9, that is E - 9 when
+// m <= 0.875 and E - 8 otherwise (no division, no search).
 __device__ inline int mx_exponent(float amax) {
     if (!(amax > 0.0f) || !isfinite(amax)) return 0;
-    int e;
-    frexpf(amax / 448.0f, &e);  // a first guess, then exact comparisons
-    e = e < -127 ? -127 : (e > 127 ? 127 : e);
-    while (e > -127 && ldexpf(448.0f, e - 1) >= amax) --e;
-    while (e < 127 && ldexpf(448.0f, e) < amax) ++e;
-    return e;
+    int E;
+    const float m = frexpf(amax, &E);
+    const int e = E - 9 + (m > 0.875f ? 1 : 0);
+    return e < -127 ? -127 : (e > 127 ? 127 : e);
 }
 
-// Store one output vector: FP32 (plus the frame's partial maximum when AMAX),
-// or, when QOUT, block-scaled FP8: the 32/VEC lanes that hold one 32-float
-// block of the frame share its maximum through a butterfly, every lane writes
-// the E4M3 codes of its VEC floats scaled by 2^-e, and the block's first lane
-// writes the E8M0 scale byte e + 127.
-template <int VEC, bool AMAX, bool QOUT, bool NT>
-__device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
-                                          int gw, int j0) {
+// v from the lane a DPP pattern names (row-local; lanes the pattern leaves
+// out read 0).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_read(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
+}
+// Maximum over aligned groups of G lanes (8, 16 or 32) of |x|, on the bit
+// patterns: for non-negative floats the unsigned order is the float order,
+// and 0 (what an absent lane reads) is the identity.  lane ^ 1, lane ^ 2
+// (quad permutes), the mirror within 8 lanes and within a 16-lane row, then
+// lane ^ 16 through the swizzle unit.
+template <int G>
+__device__ __forceinline__ float group_absmax(float x) {
+    static_assert(G == 8 || G == 16 || G == 32, "group of 8, 16 or 32 lanes");
+    uint32_t v = __builtin_bit_cast(uint32_t, fabsf(x));
+    v = max(v, dpp_read<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = max(v, dpp_read<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = max(v, dpp_read<0x141>(v));  // row_half_mirror
+    if constexpr (G >= 16) v = max(v, dpp_read<0x140>(v));  // row_mirror
+    if constexpr (G >= 32)  // ds_swizzle bit mode: and 0x1f, or 0, xor 0x10
+        v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
+    return __builtin_bit_cast(float, v);
+}
+
+// Where one block of frames goes.  PtrSink: plain pointers, row u of the
+// block at base + u * stride.  BufSink: buffer resources whose base is the
+// block's first row (wave-uniform); a lane's column offset stays in one VGPR
+// and the row offset u * stride is an SGPR, so no per-row address registers
+// are kept.  Out-of-range buffer stores are dropped by the hardware.
+template <int VEC, bool NT>
+struct PtrSink {
     using V = typename VecT<VEC>::T;
+    float* yb;
+    uint8_t* qb;
+    uint8_t* sb;
+    int64_t ldy, ldq, nsc;
+    __device__ __forceinline__ void y(int u, const V& v) const { st<NT>(reinterpret_cast<V*>(yb + u * ldy), v); }
+    __device__ __forceinline__ void q32(int u, uint32_t w) const {
+        st<NT>(reinterpret_cast<uint32_t*>(qb + u * ldq), w);
+    }
+    __device__ __forceinline__ void s8(int u, uint8_t b) const { sb[u * nsc] = b; }
+};
+
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer access
+constexpr int kNtAux = 2;              // non-temporal cache policy bit of buffer loads and stores
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+    const uint32_t n = bytes <= 0 ? 0u : (bytes >= 0xffffffffLL ? 0xffffffffu : (uint32_t)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, kBufWord3);
+}
+
+template <int VEC, bool NT>
+struct BufSink {
+    using V = typename VecT<VEC>::T;
+    __amdgpu_buffer_rsrc_t ry, rq, rs;
+    uint32_t vy, vq, vs;  // lane offsets (bytes)
+    int32_t ldy4, ldq, nsc;  // row strides (bytes)
+    __device__ __forceinline__ void y(int u, const V& v) const {
+        constexpr int aux = NT ? kNtAux : 0;
+        if constexpr (VEC == 4)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, v),
+                                                   ry, vy, u * ldy4, aux);
+        else if constexpr (VEC == 2)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v),
+                                                  ry, vy, u * ldy4, aux);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ry, vy, u * ldy4, aux);
+    }
+    __device__ __forceinline__ void q32(int u, uint32_t w) const {
+        __builtin_amdgcn_raw_buffer_store_b32(w, rq, vq, u * ldq, NT ? kNtAux : 0);
+    }
+    __device__ __forceinline__ void s8(int u, uint8_t b) const { __builtin_amdgcn_raw_buffer_store_b8(b, rs, vs, u * nsc, 0); }
+};
+
+// Load of the VEC floats at byte offset voff + row * stride4 of a buffer.
+template <int VEC, bool NT>
+__device__ __forceinline__ typename VecT<VEC>::T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, int32_t soff) {
+    using V = typename VecT<VEC>::T;
+    constexpr int aux = NT ? kNtAux : 0;
+    if constexpr (VEC == 4) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, aux));
+    else if constexpr (VEC == 2) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, aux));
+    else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
+}
+
+// Store row u of a block: FP32 (plus the frame's partial maximum when AMAX),
+// or, when QOUT, block-scaled FP8: the 32/VEC lanes that hold one 32-float
+// block of the frame share its maximum (group_absmax), every lane converts its
+// VEC floats scaled by 2^-e to E4M3 codes, 4 codes are gathered into one lane
+// for a 4-byte store, and the block's first lane writes the E8M0 scale byte
+// e + 127.  f = the frame of row u.
+template <int VEC, bool AMAX, bool QOUT, class Sink>
+__device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
+                                          int gw, const Sink& out, int u) {
     if constexpr (QOUT) {
         constexpr int GL = 32 / VEC;  // lanes per 32-float block
         float mx = 0.0f;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
-#pragma unroll
-        for (int off = GL >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        mx = group_absmax<GL>(mx);
         const int e = mx_exponent(mx);
         const float sc = ldexpf(1.0f, -e);
         float x[4];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) x[v] = fminf(fmaxf(vget<VEC>(acc, v) * sc, -448.0f), 448.0f);
-        uint8_t* dst = a.q + f * a.ldq + j0;
         if constexpr (VEC == 4) {
             int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
             w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
-            st<NT>(reinterpret_cast<int*>(dst), w);
-        } else if constexpr (VEC == 2) {
-            const int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
-            st<NT>(reinterpret_cast<uint16_t*>(dst), (uint16_t)w);
-        } else {
-            const int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false);
-            st<NT>(dst, (uint8_t)w);
+            out.q32(u, (uint32_t)w);
+        } else if constexpr (VEC == 2) {  // lane pairs: the even lane stores both
+            const uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false) & 0xffffu;
+            const uint32_t w1 = dpp_read<0xF5>(w);  // quad_perm [1, 1, 3, 3]
+            if ((col & 1) == 0) out.q32(u, w | (w1 << 16));
+        } else {  // lane quads: the first lane stores all four
+            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false) & 0xffu;
+            const uint32_t c1 = dpp_read<0x55>(c), c2 = dpp_read<0xAA>(c), c3 = dpp_read<0xFF>(c);  // lanes 1, 2, 3
+            if ((col & 3) == 0) out.q32(u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
         }
-        if ((col & (GL - 1)) == 0) a.qs[f * (a.W / 32) + j0 / 32] = (uint8_t)(e + 127);
+        if ((col & (GL - 1)) == 0) out.s8(u, (uint8_t)(e + 127));
     } else {
-        st<NT>(reinterpret_cast<V*>(a.y + f * a.ldy + j0), acc);
+        out.y(u, acc);
         fir_amax<VEC, AMAX>(a, acc, f, col, gw);
     }
 }
@@ -195,42 +285,94 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
 #pragma unroll
     for (int m = 0; m < MT; ++m) tp[m] = (EXACT || m < M) ? load_taps<VEC>(a, M, m, j0) : V(0.0f);
 
+    // Ring of the last MT input frames of this thread's columns: frame g of a
+    // block starting at fb sits in slot (g - fb) mod MT.  Frames fb - d
+    // (d = 1..M-1) must be there when a block starts.
     V win[MT];
-    // Frames f_begin - d (d = 1..M-1) go to ring slot MT - d (f_begin is a multiple of MT).
+    auto load_ring = [&](int64_t fb) {
 #pragma unroll
-    for (int d = 1; d < MT; ++d) {
-        win[MT - d] = (EXACT || d < M) ? load_frame<VEC, false>(a, a.g0 + f_begin - d, j0) : V(0.0f);
-    }
-    win[0] = V(0.0f);
+        for (int d = 1; d < MT; ++d)
+            win[MT - d] = (EXACT || d < M) ? load_frame<VEC, false>(a, a.g0 + fb - d, j0) : V(0.0f);
+    };
+    // One output frame straight from its M input frames (no ring): used for
+    // blocks that straddle the prefix/chunk boundary and for the tail, so that
+    // these rare cases need no statically unrolled copy of the block.
+    auto direct = [&](int64_t f) {
+        V acc = V(0.0f);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (EXACT || m < M) acc = __builtin_elementwise_fma(tp[m], load_frame<VEC, NT>(a, a.g0 + f - m, j0), acc);
+        return acc;
+    };
 
     // Full blocks of MT frames, loaded SB frames at a time: the SB loads of a
-    // sub-block issue before its first FMA.
+    // sub-block issue before its first FMA.  When a wave's lanes all work on
+    // the same frames (ct >= 64) and the block's first frame row lies in the
+    // chunk (so the whole block does), loads and stores go through buffer
+    // resources based at the block (BufSink) and the ring carries the input
+    // frames from block to block.  Other blocks go through pointers, choosing
+    // between prefix and chunk per load.  The choice is uniform over a frame
+    // row, so the lanes that share a block maximum of the block-scaled output
+    // take the same path.
     constexpr int SB = (VEC == 4 ? 8 : 16) < MT ? (VEC == 4 ? 8 : 16) : MT;
+    const int64_t nsc = a.W / 32;
+    auto sink_ptr = [&](int64_t fb) {
+        PtrSink<VEC, NT> o;
+        o.yb = QOUT ? nullptr : a.y + fb * a.ldy + j0;
+        o.qb = QOUT ? a.q + fb * a.ldq + j0 : nullptr;
+        o.sb = QOUT ? a.qs + fb * nsc + j0 / 32 : nullptr;
+        o.ldy = a.ldy;
+        o.ldq = a.ldq;
+        o.nsc = nsc;
+        return o;
+    };
+    bool ring_ok = false;
     int64_t fb = f_begin;
     for (; fb + MT <= f_end; fb += MT) {
-#pragma unroll
-        for (int sb = 0; sb < MT; sb += SB) {
-            V in[SB];
-#pragma unroll
-            for (int i = 0; i < SB; ++i) in[i] = load_frame<VEC, NT>(a, a.g0 + fb + sb + i, j0);
-#pragma unroll
-            for (int i = 0; i < SB; ++i) {
-                const int u = sb + i;
-                win[u] = in[i];
-                const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
-                fir_store<VEC, AMAX, QOUT, NT>(a, acc, fb + u, col, gw, j0);
+        const int64_t e_row = (a.g0 + fb + a.M - 1) * (int64_t)a.W - a.plen;  // block's first float in the chunk
+        if (ct >= 64 && e_row >= 0) {
+            if (!ring_ok) load_ring(fb);
+            ring_ok = true;
+            const int64_t fu = (int64_t)uniform64((uint64_t)fb);
+            const int64_t eu = (a.g0 + fu + a.M - 1) * (int64_t)a.W - a.plen;
+            const __amdgpu_buffer_rsrc_t rin = make_rsrc(a.chunk + eu, (a.nchunk - eu) * 4);
+            const uint32_t vin = (uint32_t)j0 * 4u;
+            const int32_t w4 = a.W * 4;
+            BufSink<VEC, NT> o;
+            if constexpr (QOUT) {
+                o.rq = make_rsrc(a.q + fu * a.ldq, (a.F - fu) * a.ldq);
+                o.rs = make_rsrc(a.qs + fu * nsc, (a.F - fu) * nsc);
+                o.vq = (uint32_t)j0;
+                o.vs = (uint32_t)(j0 / 32);
+                o.ldq = (int32_t)a.ldq;
+                o.nsc = (int32_t)nsc;
+            } else {
+                o.ry = make_rsrc(a.y + fu * a.ldy, (a.F - fu) * a.ldy * 4);
+                o.vy = (uint32_t)j0 * 4u;
+                o.ldy4 = (int32_t)(a.ldy * 4);
             }
+#pragma unroll
+            for (int sb = 0; sb < MT; sb += SB) {
+                V in[SB];
+#pragma unroll
+                for (int i = 0; i < SB; ++i) in[i] = buf_load<VEC, NT>(rin, vin, (sb + i) * w4);
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    const int u = sb + i;
+                    win[u] = in[i];
+                    const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
+                    fir_store<VEC, AMAX, QOUT>(a, acc, fb + u, col, gw, o, u);
+                }
+            }
+        } else {
+            ring_ok = false;
+            const PtrSink<VEC, NT> o = sink_ptr(fb);
+            for (int u = 0; u < MT; ++u) fir_store<VEC, AMAX, QOUT>(a, direct(fb + u), fb + u, col, gw, o, u);
         }
     }
     // Tail block.
-#pragma unroll
-    for (int u = 0; u < MT; ++u) {
-        if (fb + u < f_end) {
-            win[u] = load_frame<VEC, NT>(a, a.g0 + fb + u, j0);
-            const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
-            fir_store<VEC, AMAX, QOUT, NT>(a, acc, fb + u, col, gw, j0);
-        }
-    }
+    const PtrSink<VEC, NT> o = sink_ptr(fb);
+    for (int u = 0; u < MT && fb + u < f_end; ++u) fir_store<VEC, AMAX, QOUT>(a, direct(fb + u), fb + u, col, gw, o, u);
 }
 
 template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, bool QOUT>
