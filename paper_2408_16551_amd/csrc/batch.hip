@@ -217,11 +217,15 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         fa.cf = p->cf;
         fa.amax = form_scaled(b->form) ? b->amax + amax_off : nullptr;
         fa.nparts = p->W >= 64 ? p->W / 64 : 1;  // VEC = 1 in the batched FIR
-        if (form_mx(b->form)) {  // codes, then scales, inside the item's F * W floats
+        // Operand-form FIR output inside the item's F * W floats: E4M3 codes
+        // then scales, or the bf16 piece(s) one after the other.
+        fa.qmode = form_fir_qmode(b->form);
+        if (fa.qmode != 0) {
             fa.y = nullptr;
             fa.q = (uint8_t*)(b->ws + ws_off);
             fa.ldq = p->W;
-            fa.qs = fa.q + mx_codes_bytes(F, p->W);
+            if (form_mx(b->form)) fa.qs = fa.q + mx_codes_bytes(F, p->W);
+            if (b->form == TINA_PREC_BF16X3) fa.q1 = fa.q + F * p->W * 2;
         }
         ws_off += F * p->W;
         amax_off += F * fa.nparts;
@@ -240,6 +244,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.real_pack = p->cf == 1;
         ga.form = b->form;
         ga.Aq = fa.q;
+        ga.Aq1 = fa.q1;
         ga.Aqs = fa.qs;
         bi.fir_tf = TF;
         const int64_t runs = (F + TF - 1) / TF;
@@ -307,8 +312,9 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), form_mx(b->form), grid_fir, s));
-    if (always || b->h_table->gemm_units > 0) HIP_TRY(launch_gemm_batch(b->d_table, b->form, (int)grid_gemm, s));
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), form_fir_qmode(b->form), grid_fir, s));
+    if (always || b->h_table->gemm_units > 0)
+        HIP_TRY(launch_gemm_batch(b->d_table, b->form, form_fir_qmode(b->form) != 0, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }

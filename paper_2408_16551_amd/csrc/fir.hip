@@ -37,13 +37,15 @@ int pick_vec(const FirArgs& a) {
     // Block-scaled output: 4 floats per thread up to 16 taps (the per-block
     // maximum is then shared among 8 lanes, and a lane's 4 codes leave in one
     // store; measured faster than 1 or 2 at 16 taps).
-    if (a.q && a.M <= 16) vec = 4;
+    if (a.qmode == QM_MX && a.M <= 16) vec = 4;
     const FirTune tune = fir_tune();
     if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec;
     if (vec == 4 && a.M > 16) vec = 2;  // widest ring per vector width: 16 taps (VEC 4), 32 (VEC 2), 64 (VEC 1)
     if (vec == 2 && a.M > 32) vec = 1;
     auto out_ok = [&](int v) {
-        if (a.q) return aligned(a.q, 4) && a.ldq % 4 == 0;  // codes leave in 4-byte stores
+        if (a.qmode == QM_MX) return aligned(a.q, 4) && a.ldq % 4 == 0;  // codes leave in 4-byte stores
+        if (a.qmode != QM_NONE)  // bf16: 2 v bytes per store
+            return aligned(a.q, 2 * v) && (a.q1 == nullptr || aligned(a.q1, 2 * v)) && a.ldq % v == 0;
         return aligned(a.y, 4 * v) && a.ldy % v == 0;
     };
     while (vec > 1 && !(a.plen % vec == 0 && aligned(a.chunk, 4 * vec) && out_ok(vec) &&
@@ -98,14 +100,18 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
         const int gw = ct < 64 ? ct : 64;
         a.nparts = ct / gw;
     }
-    if (a.q) return launch_fir_mode_mx(a, vec, s);
+    if (a.qmode == QM_MX) return launch_fir_mode_mx(a, vec, s);
+    if (a.qmode == QM_BF16) return launch_fir_mode_bf16(a, vec, s);
+    if (a.qmode == QM_BF16X2) return launch_fir_mode_bf16x2(a, vec, s);
     if (a.amax) return launch_fir_mode_amax(a, vec, s);
     return launch_fir_mode_f32(a, vec, s);
 }
 
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, bool qout, int grid,
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
                             hipStream_t s) {
-    if (qout) return launch_fir_batch_mode_mx(t, max_m, all_exact, grid, s);
+    if (qmode == QM_MX) return launch_fir_batch_mode_mx(t, max_m, all_exact, grid, s);
+    if (qmode == QM_BF16) return launch_fir_batch_mode_bf16(t, max_m, all_exact, grid, s);
+    if (qmode == QM_BF16X2) return launch_fir_batch_mode_bf16x2(t, max_m, all_exact, grid, s);
     if (amax) return launch_fir_batch_mode_amax(t, max_m, all_exact, grid, s);
     return launch_fir_batch_mode_f32(t, max_m, all_exact, grid, s);
 }

@@ -13,7 +13,10 @@ namespace tina {
 
 // Output modes of the FIR: FP32 rows, FP32 rows plus per-frame partial
 // maxima (per-frame scaled forms), block-scaled FP8 codes and scales.
-enum FirOut : int { FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2 };
+enum FirOut : int { FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4 };
+// Operand-form output of the FIR (FirArgs::qmode): none (FP32 y), block-scaled
+// FP8 codes and scales, bf16 (RNE), or bf16 hi + lo (lo = RNE(y - hi)).
+enum QMode : int { QM_NONE = 0, QM_MX = 1, QM_BF16 = 2, QM_BF16X2 = 3 };
 
 // Launch-shape override for tuning sweeps: TINA_FIR_TUNE="vec,tf,nt"
 // (vec 0 and tf 0 keep the defaults, vec 1/2/4 forces the vector width where
@@ -28,9 +31,13 @@ int pick_vec(const FirArgs& a);
 hipError_t launch_fir_mode_f32(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_amax(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_mx(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_bf16(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_bf16x2(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_batch_mode_f32(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_amax(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_mx(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_bf16(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_bf16x2(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 
 namespace {
 
@@ -167,12 +174,13 @@ template <int VEC, bool NT>
 struct PtrSink {
     using V = typename VecT<VEC>::T;
     float* yb;
-    uint8_t* qb;
+    uint8_t* qb[2];   // operand pieces, at this lane's position
     uint8_t* sb;
-    int64_t ldy, ldq, nsc;
+    int64_t ldy, ldq, nsc;  // ldq in bytes
     __device__ __forceinline__ void y(int u, const V& v) const { st<NT>(reinterpret_cast<V*>(yb + u * ldy), v); }
-    __device__ __forceinline__ void q32(int u, uint32_t w) const {
-        st<NT>(reinterpret_cast<uint32_t*>(qb + u * ldq), w);
+    template <class T>
+    __device__ __forceinline__ void q(int piece, int u, T w) const {
+        st<NT>(reinterpret_cast<T*>(qb[piece] + u * ldq), w);
     }
     __device__ __forceinline__ void s8(int u, uint8_t b) const { sb[u * nsc] = b; }
 };
@@ -193,7 +201,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
 template <int VEC, bool NT>
 struct BufSink {
     using V = typename VecT<VEC>::T;
-    __amdgpu_buffer_rsrc_t ry, rq, rs;
+    __amdgpu_buffer_rsrc_t ry, rq[2], rs;
     uint32_t vy, vq, vs;  // lane offsets (bytes)
     int32_t ldy4, ldq, nsc;  // row strides (bytes)
     __device__ __forceinline__ void y(int u, const V& v) const {
@@ -207,8 +215,16 @@ struct BufSink {
         else
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ry, vy, u * ldy4, aux);
     }
-    __device__ __forceinline__ void q32(int u, uint32_t w) const {
-        __builtin_amdgcn_raw_buffer_store_b32(w, rq, vq, u * ldq, NT ? kNtAux : 0);
+    template <class T>
+    __device__ __forceinline__ void q(int piece, int u, T w) const {
+        constexpr int aux = NT ? kNtAux : 0;
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, w),
+                                                  rq[piece], vq, u * ldq, aux);
+        else if constexpr (sizeof(T) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)w, rq[piece], vq, u * ldq, aux);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w, rq[piece], vq, u * ldq, aux);
     }
     __device__ __forceinline__ void s8(int u, uint8_t b) const { __builtin_amdgcn_raw_buffer_store_b8(b, rs, vs, u * nsc, 0); }
 };
@@ -223,16 +239,22 @@ __device__ __forceinline__ typename VecT<VEC>::T buf_load(__amdgpu_buffer_rsrc_t
     else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
 }
 
+__device__ __forceinline__ uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
 // Store row u of a block: FP32 (plus the frame's partial maximum when AMAX),
-// or, when QOUT, block-scaled FP8: the 32/VEC lanes that hold one 32-float
-// block of the frame share its maximum (group_absmax), every lane converts its
-// VEC floats scaled by 2^-e to E4M3 codes, 4 codes are gathered into one lane
-// for a 4-byte store, and the block's first lane writes the E8M0 scale byte
-// e + 127.  f = the frame of row u.
-template <int VEC, bool AMAX, bool QOUT, class Sink>
+// or an operand form (QM):
+//  - QM_MX, block-scaled FP8: the 32/VEC lanes that hold one 32-float block
+//    of the frame share its maximum (group_absmax), every lane converts its
+//    VEC floats scaled by 2^-e to E4M3 codes, 4 codes are gathered into one
+//    lane for a 4-byte store, and the block's first lane writes the E8M0
+//    scale byte e + 127;
+//  - QM_BF16 / QM_BF16X2: bf16 hi = RNE(y) (and lo = RNE(y - hi)), VEC
+//    values per lane.
+// f = the frame of row u.
+template <int VEC, bool AMAX, int QM, class Sink>
 __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
                                           int gw, const Sink& out, int u) {
-    if constexpr (QOUT) {
+    if constexpr (QM == QM_MX) {
         constexpr int GL = 32 / VEC;  // lanes per 32-float block
         float mx = 0.0f;
 #pragma unroll
@@ -246,17 +268,32 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
         if constexpr (VEC == 4) {
             int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
             w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
-            out.q32(u, (uint32_t)w);
+            out.q(0, u, (uint32_t)w);
         } else if constexpr (VEC == 2) {  // lane pairs: the even lane stores both
             const uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false) & 0xffffu;
             const uint32_t w1 = dpp_read<0xF5>(w);  // quad_perm [1, 1, 3, 3]
-            if ((col & 1) == 0) out.q32(u, w | (w1 << 16));
+            if ((col & 1) == 0) out.q(0, u, w | (w1 << 16));
         } else {  // lane quads: the first lane stores all four
             const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false) & 0xffu;
             const uint32_t c1 = dpp_read<0x55>(c), c2 = dpp_read<0xAA>(c), c3 = dpp_read<0xFF>(c);  // lanes 1, 2, 3
-            if ((col & 3) == 0) out.q32(u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
+            if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
         }
         if ((col & (GL - 1)) == 0) out.s8(u, (uint8_t)(e + 127));
+    } else if constexpr (QM == QM_BF16 || QM == QM_BF16X2) {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const float x = vget<VEC>(acc, v);
+            hi[v] = bf16_bits(x);
+            lo[v] = bf16_bits(x - __builtin_bit_cast(float, hi[v] << 16));
+        }
+        auto put = [&](int piece, const uint32_t (&h)[4]) {
+            if constexpr (VEC == 4) out.q(piece, u, (uint64_t)(h[0] | (h[1] << 16)) | ((uint64_t)(h[2] | (h[3] << 16)) << 32));
+            else if constexpr (VEC == 2) out.q(piece, u, h[0] | (h[1] << 16));
+            else out.q(piece, u, (uint16_t)h[0]);
+        };
+        put(0, hi);
+        if constexpr (QM == QM_BF16X2) put(1, lo);
     } else {
         out.y(u, acc);
         fir_amax<VEC, AMAX>(a, acc, f, col, gw);
@@ -265,9 +302,9 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
 
 // MT: ring length (unroll); EXACT: M == MT (no per-tap predicate);
 // NT: non-temporal input loads and output stores (streaming cache policy);
-// QOUT: block-scaled FP8 output (a.q, a.qs) instead of FP32 (a.y).
+// QM: operand-form output (a.q, a.q1, a.qs; QMode) instead of FP32 (a.y).
 // One 256-thread unit of work: logical block `blk` of the (column, run) grid.
-template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, bool QOUT = false>
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, int QM>
 __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) {
     using V = typename VecT<VEC>::T;
     const int ct = a.W / VEC;                    // threads per frame row (power of two)
@@ -316,13 +353,15 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
     // take the same path.
     constexpr int SB = (VEC == 4 ? 8 : 16) < MT ? (VEC == 4 ? 8 : 16) : MT;
     const int64_t nsc = a.W / 32;
+    constexpr int QB = QM == QM_MX ? 1 : 2;  // bytes per operand element
     auto sink_ptr = [&](int64_t fb) {
         PtrSink<VEC, NT> o;
-        o.yb = QOUT ? nullptr : a.y + fb * a.ldy + j0;
-        o.qb = QOUT ? a.q + fb * a.ldq + j0 : nullptr;
-        o.sb = QOUT ? a.qs + fb * nsc + j0 / 32 : nullptr;
+        o.yb = QM ? nullptr : a.y + fb * a.ldy + j0;
+        o.qb[0] = QM ? a.q + (fb * a.ldq + j0) * QB : nullptr;
+        o.qb[1] = QM == QM_BF16X2 ? a.q1 + (fb * a.ldq + j0) * QB : nullptr;
+        o.sb = QM == QM_MX ? a.qs + fb * nsc + j0 / 32 : nullptr;
         o.ldy = a.ldy;
-        o.ldq = a.ldq;
+        o.ldq = a.ldq * QB;
         o.nsc = nsc;
         return o;
     };
@@ -339,12 +378,13 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
             const uint32_t vin = (uint32_t)j0 * 4u;
             const int32_t w4 = a.W * 4;
             BufSink<VEC, NT> o;
-            if constexpr (QOUT) {
-                o.rq = make_rsrc(a.q + fu * a.ldq, (a.F - fu) * a.ldq);
-                o.rs = make_rsrc(a.qs + fu * nsc, (a.F - fu) * nsc);
-                o.vq = (uint32_t)j0;
+            if constexpr (QM != QM_NONE) {
+                o.rq[0] = make_rsrc(a.q + fu * a.ldq * QB, (a.F - fu) * a.ldq * QB);
+                if constexpr (QM == QM_BF16X2) o.rq[1] = make_rsrc(a.q1 + fu * a.ldq * QB, (a.F - fu) * a.ldq * QB);
+                if constexpr (QM == QM_MX) o.rs = make_rsrc(a.qs + fu * nsc, (a.F - fu) * nsc);
+                o.vq = (uint32_t)(j0 * QB);
                 o.vs = (uint32_t)(j0 / 32);
-                o.ldq = (int32_t)a.ldq;
+                o.ldq = (int32_t)(a.ldq * QB);
                 o.nsc = (int32_t)nsc;
             } else {
                 o.ry = make_rsrc(a.y + fu * a.ldy, (a.F - fu) * a.ldy * 4);
@@ -361,41 +401,42 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
                     const int u = sb + i;
                     win[u] = in[i];
                     const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
-                    fir_store<VEC, AMAX, QOUT>(a, acc, fb + u, col, gw, o, u);
+                    fir_store<VEC, AMAX, QM>(a, acc, fb + u, col, gw, o, u);
                 }
             }
         } else {
             ring_ok = false;
             const PtrSink<VEC, NT> o = sink_ptr(fb);
-            for (int u = 0; u < MT; ++u) fir_store<VEC, AMAX, QOUT>(a, direct(fb + u), fb + u, col, gw, o, u);
+            for (int u = 0; u < MT; ++u) fir_store<VEC, AMAX, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
         }
     }
     // Tail block.
     const PtrSink<VEC, NT> o = sink_ptr(fb);
-    for (int u = 0; u < MT && fb + u < f_end; ++u) fir_store<VEC, AMAX, QOUT>(a, direct(fb + u), fb + u, col, gw, o, u);
+    for (int u = 0; u < MT && fb + u < f_end; ++u) fir_store<VEC, AMAX, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
 }
 
-template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, bool QOUT>
+template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, int QM>
 __global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
-    fir_unit<VEC, MT, EXACT, AMAX, NT, QOUT>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
+    fir_unit<VEC, MT, EXACT, AMAX, NT, QM>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 // Persistent batched FIR: each block walks its XCD's contiguous, cost-balanced
 // range of units (see BatchTable); a unit is one 256-thread block of one item.
-template <int MT, bool EXACT, bool AMAX, bool QOUT>
+template <int MT, bool EXACT, bool AMAX, int QM>
 __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __restrict__ t) {
     const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
     const int64_t end = t->fir_bounds[x + 1];
     for (int64_t u = t->fir_bounds[x] + i; u < end; u += nbx) {
         const int it = batch_find(t->items, t->n_items, u, /*stage=*/0);
         const BatchItem& b = t->items[it];
-        fir_unit<1, MT, EXACT, AMAX, true, QOUT>(b.fir, b.fir_tf, u - b.fir_unit0);
+        fir_unit<1, MT, EXACT, AMAX, true, QM>(b.fir, b.fir_tf, u - b.fir_unit0);
     }
 }
 
 template <int VEC, int MT, bool EXACT, int MODE>
 hipError_t launch_one(FirArgs& a, hipStream_t s) {
-    constexpr bool AMAX = MODE == FIR_OUT_AMAX, QOUT = MODE == FIR_OUT_MX;
+    constexpr bool AMAX = MODE == FIR_OUT_AMAX;
+    constexpr int QM = MODE == FIR_OUT_MX ? QM_MX : (MODE == FIR_OUT_BF16 ? QM_BF16 : (MODE == FIR_OUT_BF16X2 ? QM_BF16X2 : QM_NONE));
     const int ct = a.W / VEC;
     // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
     // least 16) keeps the halo re-reads in L2 while leaving enough waves to
@@ -410,12 +451,12 @@ hipError_t launch_one(FirArgs& a, hipStream_t s) {
     // FP32 mode can turn them off for tuning sweeps.
     if constexpr (MODE == FIR_OUT_F32) {
         if (tune.nt == 0) {
-            hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, false, false, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+            hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, false, false, QM_NONE>), dim3((unsigned)blocks), dim3(256), 0, s,
                                a, TF);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, true, QOUT>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
+    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, true, QM>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
     return hipGetLastError();
 }
 
@@ -451,11 +492,12 @@ hipError_t launch_mode(FirArgs& a, int vec, hipStream_t s) {
 
 template <int MODE>
 hipError_t launch_batch_mode(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
-    constexpr bool AMAX = MODE == FIR_OUT_AMAX, QOUT = MODE == FIR_OUT_MX;
+    constexpr bool AMAX = MODE == FIR_OUT_AMAX;
+    constexpr int QM = MODE == FIR_OUT_MX ? QM_MX : (MODE == FIR_OUT_BF16 ? QM_BF16 : (MODE == FIR_OUT_BF16X2 ? QM_BF16X2 : QM_NONE));
     auto go = [&](auto mt_tag) -> hipError_t {
         constexpr int MT = decltype(mt_tag)::value;
-        if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, AMAX, QOUT>), dim3(grid), dim3(256), 0, s, t);
-        else hipLaunchKernelGGL((fir_batch_kernel<MT, false, AMAX, QOUT>), dim3(grid), dim3(256), 0, s, t);
+        if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, AMAX, QM>), dim3(grid), dim3(256), 0, s, t);
+        else hipLaunchKernelGGL((fir_batch_kernel<MT, false, AMAX, QM>), dim3(grid), dim3(256), 0, s, t);
         return hipGetLastError();
     };
     if (max_m <= 1) return go(std::integral_constant<int, 1>{});

@@ -18,6 +18,8 @@
 
 #include <stdlib.h>
 
+#include <type_traits>
+
 namespace tina {
 namespace {
 
@@ -39,7 +41,7 @@ template <> struct FT<FORM_FP16X3> { static constexpr int EB = 2, NP = 2, SLAB =
 template <> struct FT<FORM_FP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = true, MX = false; };
 template <> struct FT<FORM_MXFP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = false, MX = true; };
 
-constexpr int BM = 128, BN = 128;     // block tile
+constexpr int BM = 128;               // block tile rows (frames); columns BN = 64 * WN
 constexpr int ROWB = 128;             // bytes of each operand row per K tile
 constexpr int RS = ROWB + 16;         // LDS row stride: 16-byte pad keeps 16-byte reads conflict-free
 constexpr int NT = 256;               // threads per block
@@ -64,23 +66,23 @@ __device__ inline uint32_t f16_pair(float a, float b) {
 __device__ inline float bf16_round(float a) { return (float)(__bf16)a; }
 __device__ inline float f16_round(float a) { return (float)(_Float16)a; }
 
-// The MFMAs of one K slab for the wave's 2 x 2 blocks.  Products are issued
+// The MFMAs of one K slab for the wave's 2 x WN blocks.  Products are issued
 // term-major (every block's hi*hi, then every block's hi*lo, ...), so MFMAs
 // that accumulate into the same registers are four instructions apart.
 // af[bm][piece][read], bf[bn][piece][read]: the lane's 16-byte K slices.
 // sa/sb (block-scaled form): the lane's E8M0 scale in the low byte, one per
 // 32-K block of the lane's row / column.
-template <int FORM, int NP, int RD>
-__device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[2][NP][RD],
-                                          f32x16 (&acc)[2][2], f32x16 (&acc2)[2][2], const int (&sa)[2],
-                                          const int (&sb)[2]) {
+template <int FORM, int NP, int RD, int WN>
+__device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[WN][NP][RD],
+                                          f32x16 (&acc)[2][WN], f32x16 (&acc2)[2][WN], const int (&sa)[2],
+                                          const int (&sb)[WN]) {
     if constexpr (FORM == FORM_FP32) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
+                for (int bn = 0; bn < WN; ++bn) {
                     const f32x4 av = __builtin_bit_cast(f32x4, af[bm][0][0]);
                     const f32x4 bv = __builtin_bit_cast(f32x4, bf[bn][0][0]);
                     acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[bm][bn], 0, 0, 0);
@@ -94,7 +96,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
+                for (int bn = 0; bn < WN; ++bn) {
                     const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
                     const bf16x8 a = __builtin_bit_cast(bf16x8, af[bm][pa < NP ? pa : 0][0]);
                     const bf16x8 b = __builtin_bit_cast(bf16x8, bf[bn][pb < NP ? pb : 0][0]);
@@ -108,7 +110,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
+                for (int bn = 0; bn < WN; ++bn) {
                     const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
                     const f16x8 a = __builtin_bit_cast(f16x8, af[bm][pa < NP ? pa : 0][0]);
                     const f16x8 b = __builtin_bit_cast(f16x8, bf[bn][pb < NP ? pb : 0][0]);
@@ -119,7 +121,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 #pragma unroll
         for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-            for (int bn = 0; bn < 2; ++bn) {
+            for (int bn = 0; bn < WN; ++bn) {
                 i32x8 av, bv;
                 const uint4 a0 = af[bm][0][0], a1 = af[bm][0][RD - 1];
                 const uint4 b0 = bf[bn][0][0], b1 = bf[bn][0][RD - 1];
@@ -139,17 +141,17 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
     }
 }
 
-template <int FORM>
+template <int FORM, int WN>
 struct GemmSmem {
-    static constexpr int NP = FT<FORM>::NP;
-    uint8_t tiles[2 * NP * BM * RS];  // NP A pieces then NP B pieces, BM (= BN) rows of RS bytes
-    float inv[BM], sc[BM];            // per-frame scale and its inverse
+    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN;
+    uint8_t tiles[NP * (BM + BN) * RS];  // NP A pieces (BM rows), then NP B pieces (BN rows), RS bytes a row
+    float inv[BM], sc[BM];               // per-frame scale and its inverse
     uint32_t mxs[FT<FORM>::MX ? BM + BN : 1];  // block scales of the K tile: 4 bytes per A row, then B row
 };
 
 // Map a logical tile index L of an nm x nn grid: groups of GROUP_M m-tiles
 // sweep all n-tiles, so they share each B column block and their A rows.
-__device__ inline void grouped_tile(int64_t L, int64_t nm, int64_t nn, int64_t& m0, int64_t& n0) {
+__device__ inline void grouped_tile(int64_t L, int64_t nm, int64_t nn, int BN, int64_t& m0, int64_t& n0) {
     const int64_t gsz_full = GROUP_M * nn;
     const int64_t grp = L / gsz_full, first_m = grp * GROUP_M;
     const int64_t gsz = min((int64_t)GROUP_M, nm - first_m);
@@ -158,14 +160,51 @@ __device__ inline void grouped_tile(int64_t L, int64_t nm, int64_t nn, int64_t& 
     n0 = (within / gsz) * BN;
 }
 
-// One BM x BN output tile at (m0, n0).  Called by every thread of the block.
-template <int FORM>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM>& sm) {
+// Epilogue of a tile: combine pieces, undo the frame scale (s_sc, per-frame
+// scaled forms), write complex64 rows.
+template <int FORM, int WN>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int64_t n0, const f32x16 (&acc)[2][WN],
+                                              const f32x16 (&acc2)[2][WN], const float* s_sc) {
+    using ft = FT<FORM>;
+    constexpr int WC = 32 * WN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 31, lh = lane >> 5;
+    const float corr = (FORM == FORM_FP16X3) ? (1.0f / 2048.0f) : 1.0f;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+            const int64_t col = n0 + wn * WC + bn * 32 + lr;
+            if (col >= g.N) continue;
+            int64_t oc = col;
+            if (g.real_pack) oc = col >= 2 ? col : (col == 0 ? 0 : (int64_t)g.N);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int rloc = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3);
+                const int64_t row = m0 + rloc;
+                if (row >= g.F) continue;
+                float val = acc[bm][bn][v];
+                if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
+                if constexpr (ft::SCALED) val *= s_sc[rloc];
+                float* o = g.out + row * g.ldo;
+                o[oc] = val;
+                if (g.real_pack && col < 2) o[oc + 1] = 0.0f;  // Im X_0, Im X_{P/2}
+            }
+        }
+}
+
+
+// One BM x BN output tile at (m0, n0), BN = 64 * WN: 2 x 2 waves, each
+// 64 x 32 WN as 2 x WN MFMA blocks.  Called by every thread of the block.
+template <int FORM, int WN>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM, WN>& sm) {
+    constexpr int BN = 64 * WN, WC = 32 * WN;  // block tile columns, columns per wave
     using ft = FT<FORM>;
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
     constexpr int BK = ROWB / EB;                 // K elements per tile
     constexpr int ACPR = BK / 4;                  // A float4 chunks per row
-    constexpr int ACH = ft::MX ? 1 : BM * ACPR / NT;  // A float4 chunks per thread (FP32 A)
+    constexpr int ACH = BM * ACPR / NT;           // A float4 chunks per thread (FP32 A)
     constexpr int BCH = BN * (ROWB / 16) / NT;    // B 16-byte chunks per thread per piece
     constexpr int NSLAB = ROWB / SLAB;
     constexpr int RD = SLAB / 32;                 // 16-byte reads per lane per slab
@@ -194,42 +233,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         __syncthreads();
     }
 
-    static_assert(!ft::MX || (BM + BN == NT && NP == 1), "block-scaled form: one scale word per thread");
+    static_assert(!ft::MX, "the block-scaled form takes the raw-operand tile");
     float4 ra[ACH];
     uint4 rb[NP][BCH];
-    uint4 rqa[ft::MX ? BCH : 1];  // block-scaled form: A codes
-    uint32_t rsc = 0;             // block-scaled form: this thread's scale word
     const uint8_t* Bp[2] = {(const uint8_t*)g.B0, (const uint8_t*)g.B1};
     const int64_t KB = (int64_t)g.K * EB;  // bytes per Bt row
 
     auto load_tile = [&](int k0) {
-        if constexpr (ft::MX) {
-            // K % 128 == 0 (checked at plan time): every K tile is whole.
-#pragma unroll
-            for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-                const int64_t f = m0 + row;
-                rqa[i] = f < g.F ? *reinterpret_cast<const uint4*>(g.Aq + f * g.lda + k0 + kc * 16)
-                                 : make_uint4(0u, 0u, 0u, 0u);
-            }
-            const int64_t nb = g.K / 32;
-            if (tid < BM) {
-                const int64_t f = m0 + tid;
-                rsc = f < g.F ? *reinterpret_cast<const uint32_t*>(g.Aqs + f * nb + k0 / 32) : 0x7f7f7f7fu;
-            } else {
-                const int64_t n = n0 + tid - BM;
-                rsc = n < g.N ? *reinterpret_cast<const uint32_t*>((const uint8_t*)g.B1 + n * nb + k0 / 32)
-                              : 0x7f7f7f7fu;
-            }
-#pragma unroll
-            for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-                const int64_t n = n0 + row;
-                rb[0][i] = n < g.N ? *reinterpret_cast<const uint4*>(Bp[0] + n * KB + (int64_t)k0 + kc * 16)
-                                   : make_uint4(0u, 0u, 0u, 0u);
-            }
-            return;
-        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) {
             const int c = tid + i * NT, row = c / ACPR, kc = c % ACPR;
@@ -251,16 +261,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     };
 
     auto store_tile = [&]() {
-        if constexpr (ft::MX) {
-#pragma unroll
-            for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
-                *reinterpret_cast<uint4*>(As + row * RS + kc * 16) = rqa[i];
-                *reinterpret_cast<uint4*>(Bs + row * RS + kc * 16) = rb[0][i];
-            }
-            sm.mxs[tid] = rsc;
-            return;
-        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) {
             const int c = tid + i * NT, row = c / ACPR, kc = c % ACPR;
@@ -302,11 +302,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
             }
     };
 
-    f32x16 acc[2][2], acc2[2][2];
+    f32x16 acc[2][WN], acc2[2][WN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) { acc[i][j][v] = 0.f; acc2[i][j][v] = 0.f; }
 
@@ -318,12 +318,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         if (t + 1 < nk) load_tile((t + 1) * BK);
 #pragma unroll
         for (int s = 0; s < NSLAB; ++s) {
-            uint4 af[2][NP][RD], bf[2][NP][RD];
-            // The lane's 16-byte reads of the slab.  For the 64-K FP8 MFMA
-            // this puts the instruction's K index equal to the byte offset in
-            // the slab (bytes 0-15 of lane half lh are K 16 lh.., bytes 16-31
-            // are K 32 + 16 lh..), so its 32-K scale block b is bytes
-            // [32 b, 32 b + 32) of the slab, whose scale lane half b supplies.
+            uint4 af[2][NP][RD], bf[WN][NP][RD];
             auto off = [&](int q) { return s * SLAB + q * 32 + lh * 16; };
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
@@ -335,24 +330,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                         af[bm][p][q] = *reinterpret_cast<const uint4*>(As + p * BM * RS + row * RS + off(q));
                     }
 #pragma unroll
-            for (int bn = 0; bn < 2; ++bn)
+            for (int bn = 0; bn < WN; ++bn)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
 #pragma unroll
                     for (int q = 0; q < RD; ++q) {
-                        const int row = wn * 64 + bn * 32 + lr;
+                        const int row = wn * WC + bn * 32 + lr;
                         bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + off(q));
                     }
-            int sa[2] = {0, 0}, sb[2] = {0, 0};
-            if constexpr (ft::MX) {
-                const int sh = 8 * (2 * s + lh);  // byte of the word = 32-K block of the K tile
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    sa[b] = (int)(sm.mxs[wm * 64 + b * 32 + lr] >> sh);
-                    sb[b] = (int)(sm.mxs[BM + wn * 64 + b * 32 + lr] >> sh);
-                }
-            }
-            mfma_slab<FORM, NP, RD>(af, bf, acc, acc2, sa, sb);
+            const int sa[2] = {0, 0}, sb[WN] = {};
+            mfma_slab<FORM, NP, RD, WN>(af, bf, acc, acc2, sa, sb);
         }
         __syncthreads();
         if (t + 1 < nk) {
@@ -361,48 +348,198 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         }
     }
 
-    // Epilogue: combine pieces, undo the frame scale, write complex64 rows.
-    const float corr = (FORM == FORM_FP16X3) ? (1.0f / 2048.0f) : 1.0f;
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn) {
-            const int64_t col = n0 + wn * 64 + bn * 32 + lr;
-            if (col >= g.N) continue;
-            int64_t oc = col;
-            if (g.real_pack) oc = col >= 2 ? col : (col == 0 ? 0 : (int64_t)g.N);
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int rloc = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3);
-                const int64_t row = m0 + rloc;
-                if (row >= g.F) continue;
-                float val = acc[bm][bn][v];
-                if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
-                if constexpr (ft::SCALED) val *= s_sc[rloc];
-                float* o = g.out + row * g.ldo;
-                o[oc] = val;
-                if (g.real_pack && col < 2) o[oc + 1] = 0.0f;  // Im X_0, Im X_{P/2}
-            }
-        }
+    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, s_sc);
 }
 
-template <int FORM>
+// Raw-operand tile: A arrives in the operand form (NP pieces of EB-byte
+// elements, K contiguous, row stride g.lda elements; block-scaled FP8 also
+// with a scale byte per 32 K), so a K tile of A is copied to LDS like B, with
+// no conversion and a quarter (FP8) or half (bf16) of the FP32 A registers.
+// One-piece forms keep two LDS buffers, so one barrier per K tile suffices
+// and the stores of tile t + 1 overlap other waves' products on tile t;
+// two-piece forms keep one buffer (two barriers).
+template <int FORM, int WN>
+struct RawSmem {
+    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN, LB = NP == 1 ? 2 : 1;
+    uint8_t tiles[LB][NP * (BM + BN) * RS];
+    uint32_t mxs[LB][FT<FORM>::MX ? BM + BN : 1];  // scale words of the K tile: A rows, then B rows
+};
+
+template <int FORM, int WN>
+__device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int64_t n0, RawSmem<FORM, WN>& sm) {
+    using ft = FT<FORM>;
+    constexpr int BN = 64 * WN, WC = 32 * WN;
+    constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB, LB = RawSmem<FORM, WN>::LB;
+    constexpr int BK = ROWB / EB;               // K elements per tile
+    constexpr int QCH = BM * (ROWB / 16) / NT;  // A 16-byte chunks per thread per piece
+    constexpr int BCH = BN * (ROWB / 16) / NT;  // B 16-byte chunks per thread per piece
+    constexpr int NSLAB = ROWB / SLAB;
+    constexpr int RD = SLAB / 32;
+    static_assert(!ft::SCALED, "per-frame scaled forms convert A in the tile");
+    static_assert(!ft::MX || (BM + BN == NT && NP == 1), "block-scaled form: one scale word per thread");
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 31, lh = lane >> 5;
+    const uint8_t* Ap[2] = {g.Aq, g.Aq1};
+    const uint8_t* Bp[2] = {(const uint8_t*)g.B0, (const uint8_t*)g.B1};
+    const int64_t AB = g.lda * EB, KB = (int64_t)g.K * EB;  // bytes per A row, valid bytes per row
+    const int64_t nb = g.K / 32;                             // scale bytes per row (block-scaled form)
+
+    struct Stage {
+        uint4 a[NP][QCH];
+        uint4 b[NP][BCH];
+        uint32_t sc;
+    };
+    auto load = [&](Stage& r, int k0) {
+        const int64_t kb0 = (int64_t)k0 * EB;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int i = 0; i < QCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int64_t f = m0 + row, kb = kb0 + kc * 16;
+                r.a[p][i] = (f < g.F && kb < KB) ? *reinterpret_cast<const uint4*>(Ap[p] + f * AB + kb)
+                                                 : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int64_t n = n0 + row, kb = kb0 + kc * 16;
+                r.b[p][i] = (n < g.N && kb < KB) ? *reinterpret_cast<const uint4*>(Bp[p] + n * KB + kb)
+                                                 : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+        if constexpr (ft::MX) {  // K % 128 == 0 (checked at plan time): whole 4-byte scale words
+            if (tid < BM) {
+                const int64_t f = m0 + tid;
+                r.sc = f < g.F ? *reinterpret_cast<const uint32_t*>(g.Aqs + f * nb + k0 / 32) : 0x7f7f7f7fu;
+            } else {
+                const int64_t n = n0 + tid - BM;
+                r.sc = n < g.N ? *reinterpret_cast<const uint32_t*>((const uint8_t*)g.B1 + n * nb + k0 / 32)
+                               : 0x7f7f7f7fu;
+            }
+        }
+    };
+    auto store = [&](const Stage& r, int buf) {
+        uint8_t* As = sm.tiles[buf];
+        uint8_t* Bs = sm.tiles[buf] + NP * BM * RS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int i = 0; i < QCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                *reinterpret_cast<uint4*>(As + p * BM * RS + row * RS + kc * 16) = r.a[p][i];
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = r.b[p][i];
+            }
+        }
+        if constexpr (ft::MX) sm.mxs[buf][tid] = r.sc;
+    };
+
+    static_assert(FORM != FORM_FP16X3, "the second accumulator is not kept here");
+    f32x16 acc[2][WN], acc2[2][WN];  // acc2 is never read or written by these forms
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    auto compute = [&](int buf) {
+        const uint8_t* As = sm.tiles[buf];
+        const uint8_t* Bs = sm.tiles[buf] + NP * BM * RS;
+#pragma unroll
+        for (int s = 0; s < NSLAB; ++s) {
+            uint4 af[2][NP][RD], bf[WN][NP][RD];
+            // For the 64-K FP8 MFMA these reads make the instruction's K index
+            // equal to the byte offset in the slab (bytes 0-15 of lane half lh
+            // are K 16 lh.., bytes 16-31 are K 32 + 16 lh..), so its 32-K scale
+            // block b is bytes [32 b, 32 b + 32) of the slab, whose scale lane
+            // half b supplies.
+            auto off = [&](int q) { return s * SLAB + q * 32 + lh * 16; };
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int q = 0; q < RD; ++q)
+                        af[bm][p][q] = *reinterpret_cast<const uint4*>(As + p * BM * RS + (wm * 64 + bm * 32 + lr) * RS + off(q));
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int q = 0; q < RD; ++q)
+                        bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + (wn * WC + bn * 32 + lr) * RS + off(q));
+            int sa[2] = {0, 0}, sb[WN] = {};
+            if constexpr (ft::MX) {
+                const int sh = 8 * (2 * s + lh);  // byte of the word = 32-K block of the K tile
+#pragma unroll
+                for (int b = 0; b < 2; ++b) sa[b] = (int)(sm.mxs[buf][wm * 64 + b * 32 + lr] >> sh);
+#pragma unroll
+                for (int b = 0; b < WN; ++b) sb[b] = (int)(sm.mxs[buf][BM + wn * WC + b * 32 + lr] >> sh);
+            }
+            mfma_slab<FORM, NP, RD, WN>(af, bf, acc, acc2, sa, sb);
+        }
+    };
+
+    __syncthreads();  // the previous tile of a persistent block is done with LDS
+    const int nk = (g.K + BK - 1) / BK;
+    Stage r;
+    load(r, 0);
+    store(r, 0);
+    if (nk > 1) load(r, BK);
+    __syncthreads();
+    // Tile t sits in LDS buffer t % LB.  While tile t is multiplied, the
+    // registers hold tile t + 1; it is then stored to the other buffer and the
+    // loads of tile t + 2 are issued.
+    for (int t = 0; t < nk; ++t) {
+        compute(LB == 2 ? (t & 1) : 0);
+        if constexpr (LB == 1) __syncthreads();
+        if (t + 1 < nk) {
+            store(r, LB == 2 ? ((t + 1) & 1) : 0);
+            if (t + 2 < nk) load(r, (t + 2) * BK);
+        }
+        __syncthreads();
+    }
+    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, nullptr);
+}
+
+template <int FORM, int WN>
 __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) GemmSmem<FORM> sm;
+    constexpr int BN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) GemmSmem<FORM, WN> sm;
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
     int64_t m0, n0;
-    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, m0, n0);
-    gemm_tile<FORM>(g, m0, n0, sm);
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, BN, m0, n0);
+    gemm_tile<FORM, WN>(g, m0, n0, sm);
+}
+
+template <int FORM, int WN>
+__global__ __launch_bounds__(NT) void dft_gemm_raw_kernel(GemmArgs g) {
+    constexpr int BN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) RawSmem<FORM, WN> sm;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, BN, m0, n0);
+    gemm_tile_raw<FORM, WN>(g, m0, n0, sm);
 }
 
 // Batched GEMM, one block per tile of any item: block b serves tile
 // i = b / 8 of XCD x = b % 8's contiguous, cost-balanced range of tiles (see
 // BatchTable); blocks past the end of their range return at once.  (A
 // persistent loop over tiles keeps per-tile state live across iterations and
-// halves the occupancy, so each block does one tile.)
-template <int FORM>
+// halves the occupancy, so each block does one tile.)  RAW: A in operand form.
+template <int FORM, bool RAW>
 __global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __restrict__ t) {
-    __shared__ __attribute__((aligned(16))) GemmSmem<FORM> sm;
+    constexpr int WN = kGemmBN / 64, BN = kGemmBN;
+    static_assert(kGemmBM == BM, "batch planner and kernel agree on the tile");
+    using Smem = std::conditional_t<RAW, RawSmem<FORM, WN>, GemmSmem<FORM, WN>>;
+    __shared__ __attribute__((aligned(16))) Smem sm;
     const int x = blockIdx.x & 7;
     const int64_t u = t->gemm_bounds[x] + (blockIdx.x >> 3);
     if (u >= t->gemm_bounds[x + 1]) return;
@@ -410,28 +547,52 @@ __global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __
     const GemmArgs& g = t->items[it].gemm;
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
     int64_t m0, n0;
-    grouped_tile(u - t->items[it].gemm_unit0, nm, nn, m0, n0);
-    gemm_tile<FORM>(g, m0, n0, sm);
+    grouped_tile(u - t->items[it].gemm_unit0, nm, nn, BN, m0, n0);
+    if constexpr (RAW) gemm_tile_raw<FORM, WN>(g, m0, n0, sm);
+    else gemm_tile<FORM, WN>(g, m0, n0, sm);
+}
+
+// Columns per wave: 4 MFMA blocks (128 x 256 tiles) for FP32, whose long
+// K tiles hide latency at 2 blocks per CU and whose tile count then fills the
+// chip in whole rounds; 2 (128 x 128) for the others.
+template <int FORM>
+hipError_t launch_form(const GemmArgs& g, hipStream_t s) {
+    constexpr int WN = FORM == FORM_FP32 ? 4 : 2, BN = 64 * WN;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    hipLaunchKernelGGL((dft_gemm_kernel<FORM, WN>), dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
+    return hipGetLastError();
 }
 
 template <int FORM>
-hipError_t launch_form(const GemmArgs& g, hipStream_t s) {
+hipError_t launch_raw(const GemmArgs& g, hipStream_t s) {
+    constexpr int WN = 2, BN = 64 * WN;
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL(dft_gemm_kernel<FORM>, dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((dft_gemm_raw_kernel<FORM, WN>), dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_t s) {
+bool gemm_raw_form(int form) { return form == FORM_MXFP8 || form == FORM_BF16 || form == FORM_BF16X3; }
+
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int grid, hipStream_t s) {
+    const dim3 gd(grid), bd(NT);
+    if (raw) {
+        switch (form) {
+            case FORM_BF16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16, true>), gd, bd, 0, s, t); break;
+            case FORM_BF16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16X3, true>), gd, bd, 0, s, t); break;
+            case FORM_MXFP8: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_MXFP8, true>), gd, bd, 0, s, t); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (form) {
-        case FORM_FP32: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP32>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_BF16: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_BF16>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_BF16X3: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_BF16X3>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_FP16: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_FP16X3: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP16X3>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_FP8: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_FP8>, dim3(grid), dim3(NT), 0, s, t); break;
-        case FORM_MXFP8: hipLaunchKernelGGL(dft_gemm_batch_kernel<FORM_MXFP8>, dim3(grid), dim3(NT), 0, s, t); break;
+        case FORM_FP32: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP32, false>), gd, bd, 0, s, t); break;
+        case FORM_BF16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16, false>), gd, bd, 0, s, t); break;
+        case FORM_BF16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16X3, false>), gd, bd, 0, s, t); break;
+        case FORM_FP16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16, false>), gd, bd, 0, s, t); break;
+        case FORM_FP16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16X3, false>), gd, bd, 0, s, t); break;
+        case FORM_FP8: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP8, false>), gd, bd, 0, s, t); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -439,6 +600,14 @@ hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_
 
 hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
     if (g.F <= 0) return hipSuccess;
+    if (g.Aq) {  // A in operand form
+        switch (g.form) {
+            case FORM_BF16: return launch_raw<FORM_BF16>(g, s);
+            case FORM_BF16X3: return g.Aq1 ? launch_raw<FORM_BF16X3>(g, s) : hipErrorInvalidValue;
+            case FORM_MXFP8: return (g.K % 128 == 0 && g.Aqs) ? launch_raw<FORM_MXFP8>(g, s) : hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (g.form) {
         case FORM_FP32: return launch_form<FORM_FP32>(g, s);
         case FORM_BF16: return launch_form<FORM_BF16>(g, s);
@@ -446,7 +615,6 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
         case FORM_FP16: return launch_form<FORM_FP16>(g, s);
         case FORM_FP16X3: return launch_form<FORM_FP16X3>(g, s);
         case FORM_FP8: return launch_form<FORM_FP8>(g, s);
-        case FORM_MXFP8: return (g.K % 128 == 0) ? launch_form<FORM_MXFP8>(g, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

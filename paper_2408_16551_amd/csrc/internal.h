@@ -60,9 +60,14 @@ struct FirArgs {
     int32_t P, M, cf;     // channels, taps, floats per sample
     float* amax;          // optional per-frame partial |y| maxima [F][nparts]
     int32_t nparts;       // filled in by launch_fir
-    uint8_t* q;           // block-scaled FP8 output instead of y (nullptr: FP32 y):
-    int64_t ldq;          //   E4M3 codes [F][ldq bytes] and
-    uint8_t* qs;          //   E8M0 scales [F][W/32] (one per 32 floats of a frame)
+    // Operand-form output instead of y (qmode != 0): piece 0 at q and piece 1
+    // at q1, [F][ldq elements] each; qmode 1 block-scaled FP8 (E4M3 codes plus
+    // E8M0 scales [F][W/32] at qs), 2 bf16, 3 bf16 hi + lo.
+    uint8_t* q;
+    uint8_t* q1;
+    int64_t ldq;
+    uint8_t* qs;
+    int32_t qmode;
 };
 // Chooses the vector width and unroll; returns the number of partial maxima
 // per frame through a.nparts when a.amax is set.
@@ -88,10 +93,16 @@ struct GemmArgs {
     int32_t K, N;
     int32_t real_pack;     // real input: column 0 -> X_0, column 1 -> X_{P/2}, rest in place
     int32_t form;
-    const uint8_t* Aq;     // FORM_MXFP8: A as E4M3 codes [F][lda bytes] ...
-    const uint8_t* Aqs;    //   ... and E8M0 scales [F][K/32]; B0/B1 = Bt codes / scales
+    // A already in operand form (raw-operand forms; nullptr: FP32 A above,
+    // converted in the tile): piece 0 / piece 1 [F][lda elements], and for
+    // FORM_MXFP8 the E8M0 scales [F][K/32] (then B0/B1 = Bt codes / scales).
+    const uint8_t* Aq;
+    const uint8_t* Aq1;
+    const uint8_t* Aqs;
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
+// Forms whose A the FIR can write in operand form.
+bool gemm_raw_form(int form);
 
 // ------------------------------------------------------------- factored DFT
 struct FftArgs {
@@ -151,9 +162,13 @@ __device__ inline int batch_find(const BatchItem* items, int n, int64_t u, int s
 // GEMM tile geometry shared with the batch planner.
 constexpr int kGemmBM = 128, kGemmBN = 128;
 
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, bool qout, int grid,
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
                              hipStream_t s);
-hipError_t launch_gemm_batch(const BatchTable* t, int form, int grid, hipStream_t s);
+// FirArgs::qmode the FIR writes for a DFT form (0: FP32 y).
+inline int form_fir_qmode(int form) {
+    return form == FORM_MXFP8 ? 1 : (form == FORM_BF16 ? 2 : (form == FORM_BF16X3 ? 3 : 0));
+}
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int grid, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s);
 
 }  // namespace tina

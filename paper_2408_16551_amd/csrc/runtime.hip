@@ -261,11 +261,15 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.g0 = c0;
             fa.F = Fc;
             fa.amax = form_scaled(form) ? p->amax : nullptr;
-            if (form_mx(form)) {  // codes, then scales, in the FP32 workspace (4 bytes per float)
+            // Operand-form FIR output in the FP32 workspace (4 bytes per float):
+            // E4M3 codes then scales, or the bf16 piece(s) one after the other.
+            fa.qmode = form_fir_qmode(form);
+            if (fa.qmode != 0) {
                 fa.y = nullptr;
                 fa.q = (uint8_t*)p->ws;
                 fa.ldq = p->W;
-                fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
+                if (form_mx(form)) fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
+                if (form == TINA_PREC_BF16X3) fa.q1 = (uint8_t*)p->ws + (int64_t)p->ch_frames * p->W * 2;
             }
             HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
             if (p->dft_algorithm == TINA_DFT_FACTORED) {
@@ -299,6 +303,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             ga.real_pack = p->cf == 1;
             ga.form = form;
             ga.Aq = fa.q;
+            ga.Aq1 = fa.q1;
             ga.Aqs = fa.qs;
             HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
