@@ -216,7 +216,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         fa.M = p->M;
         fa.cf = p->cf;
         fa.amax = form_scaled(b->form) ? b->amax + amax_off : nullptr;
-        fa.nparts = p->W >= 64 ? p->W / 64 : 1;  // VEC = 1 in the batched FIR
+        fa.nparts = p->W >= 32 ? p->W / 32 : 1;  // VEC = 1 in the batched FIR: one part per 32 lanes
         // Operand-form FIR output inside the item's F * W floats: E4M3 codes
         // then scales, or the bf16 piece(s) one after the other.
         fa.qmode = form_fir_qmode(b->form);
@@ -284,7 +284,7 @@ std::vector<GroupPlan> make_groups(tina_pfb_batch_s* b, tina_pfb_work* w, const 
     for (int i = 0; i < n; ++i) {
         const tina_pfb_plan_s* p = w[i].plan;
         const int64_t need = frames[i] * p->W;
-        const int64_t need_amax = frames[i] * (p->W >= 64 ? p->W / 64 : 1);
+        const int64_t need_amax = frames[i] * (p->W >= 32 ? p->W / 32 : 1);
         if (i > first && (used + need > b->ws_floats || (b->amax && used_amax + need_amax > b->amax_floats))) {
             gs.push_back({first, i - first});
             first = i;
@@ -463,7 +463,7 @@ tina_status tina_pfb_batch_create(int device, int precision, int max_items, int6
     };
     if (hipMalloc(&b->ws, b->ws_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: workspace");
     if (form_scaled(precision)) {
-        b->amax_floats = b->ws_floats / 16 + 1024;  // F * max(1, W/64) <= F * W / 16 for W >= 16
+        b->amax_floats = b->ws_floats / 16 + 1024;  // F * max(1, W/32) <= F * W / 16 for W >= 16
         if (hipMalloc(&b->amax, b->amax_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: scale workspace");
     }
     if (hipMalloc(&b->d_table, b->table_bytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: table");

@@ -88,7 +88,7 @@ hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s) {
 
 int fir_amax_parts(const FirArgs& a) {
     const int ct = a.W / pick_vec(a);
-    const int gw = ct < 64 ? ct : 64;
+    const int gw = ct < 32 ? ct : 32;
     return ct / gw;
 }
 
@@ -97,7 +97,7 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
     const int vec = pick_vec(a);
     {
         const int ct = a.W / vec;
-        const int gw = ct < 64 ? ct : 64;
+        const int gw = ct < 32 ? ct : 32;
         a.nparts = ct / gw;
     }
     if (a.qmode == QM_MX) return launch_fir_mode_mx(a, vec, s);

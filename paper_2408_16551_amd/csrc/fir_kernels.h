@@ -117,17 +117,6 @@ __device__ __forceinline__ typename VecT<VEC>::T fir_point(const typename VecT<V
     return acc;
 }
 
-template <int VEC, bool AMAX>
-__device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
-                                         int gw) {
-    if constexpr (AMAX) {
-        float mx = 0.0f;
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
-        for (int off = gw >> 1; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, gw));
-        if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
-    }
-}
 
 // Smallest e in [-127, 127] with amax <= 448 * 2^e (0 for a zero or
 // non-finite amax): the block scale of the block-scaled FP8 output.  With
@@ -147,18 +136,18 @@ template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_read(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
 }
-// Maximum over aligned groups of G lanes (8, 16 or 32) of |x|, on the bit
+// Maximum over aligned groups of G lanes (1 to 32) of |x|, on the bit
 // patterns: for non-negative floats the unsigned order is the float order,
 // and 0 (what an absent lane reads) is the identity.  lane ^ 1, lane ^ 2
 // (quad permutes), the mirror within 8 lanes and within a 16-lane row, then
 // lane ^ 16 through the swizzle unit.
 template <int G>
 __device__ __forceinline__ float group_absmax(float x) {
-    static_assert(G == 8 || G == 16 || G == 32, "group of 8, 16 or 32 lanes");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group of 1 to 32 lanes");
     uint32_t v = __builtin_bit_cast(uint32_t, fabsf(x));
-    v = max(v, dpp_read<0xB1>(v));   // quad_perm [1, 0, 3, 2]
-    v = max(v, dpp_read<0x4E>(v));   // quad_perm [2, 3, 0, 1]
-    v = max(v, dpp_read<0x141>(v));  // row_half_mirror
+    if constexpr (G >= 2) v = max(v, dpp_read<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    if constexpr (G >= 4) v = max(v, dpp_read<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    if constexpr (G >= 8) v = max(v, dpp_read<0x141>(v));  // row_half_mirror
     if constexpr (G >= 16) v = max(v, dpp_read<0x140>(v));  // row_mirror
     if constexpr (G >= 32)  // ds_swizzle bit mode: and 0x1f, or 0, xor 0x10
         v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
@@ -239,6 +228,28 @@ __device__ __forceinline__ typename VecT<VEC>::T buf_load(__amdgpu_buffer_rsrc_t
     else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
 }
 
+// Per-frame partial maxima of |y| for the per-frame scaled forms: the gw
+// lanes (a power of two up to 32) that hold one part of a frame row reduce
+// their maxima with group_absmax, and the part's first lane stores it.
+template <int VEC, bool AMAX>
+__device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
+                                         int gw) {
+    if constexpr (AMAX) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
+        switch (gw) {
+            case 32: mx = group_absmax<32>(mx); break;
+            case 16: mx = group_absmax<16>(mx); break;
+            case 8: mx = group_absmax<8>(mx); break;
+            case 4: mx = group_absmax<4>(mx); break;
+            case 2: mx = group_absmax<2>(mx); break;
+            default: break;
+        }
+        if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
+    }
+}
+
 __device__ __forceinline__ uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
 // Store row u of a block: FP32 (plus the frame's partial maximum when AMAX),
@@ -316,7 +327,7 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
     const int64_t f_end = min(a.F, f_begin + TF);
     const int j0 = col * VEC;
     const int M = EXACT ? MT : a.M;
-    const int gw = ct < 64 ? ct : 64;            // lanes sharing one frame row in a wave
+    const int gw = ct < 32 ? ct : 32;            // lanes sharing one partial maximum of a frame row
 
     V tp[MT];
 #pragma unroll

@@ -39,6 +39,9 @@ template <> struct FT<FORM_BF16X3> { static constexpr int EB = 2, NP = 2, SLAB =
 template <> struct FT<FORM_FP16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
 template <> struct FT<FORM_FP16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
 template <> struct FT<FORM_FP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = true, MX = false; };
+// Operand bytes per row and K tile in the converting tile: 128, or 64 for FP8
+// (its FP32 A prefetch would otherwise hold 64 registers per lane).
+template <int FORM> constexpr int kRowB = FORM == FORM_FP8 ? 64 : 128;
 template <> struct FT<FORM_MXFP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = false, MX = true; };
 
 constexpr int BM = 128;               // block tile rows (frames); columns BN = 64 * WN
@@ -143,8 +146,8 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 
 template <int FORM, int WN>
 struct GemmSmem {
-    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN;
-    uint8_t tiles[NP * (BM + BN) * RS];  // NP A pieces (BM rows), then NP B pieces (BN rows), RS bytes a row
+    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN, RSF = kRowB<FORM> + 16;
+    uint8_t tiles[NP * (BM + BN) * RSF];  // NP A pieces (BM rows), then NP B pieces (BN rows), RSF bytes a row
     float inv[BM], sc[BM];               // per-frame scale and its inverse
     uint32_t mxs[FT<FORM>::MX ? BM + BN : 1];  // block scales of the K tile: 4 bytes per A row, then B row
 };
@@ -202,6 +205,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     constexpr int BN = 64 * WN, WC = 32 * WN;  // block tile columns, columns per wave
     using ft = FT<FORM>;
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
+    constexpr int ROWB = kRowB<FORM>, RS = ROWB + 16, CPR = ROWB / 16;  // 16-byte chunks per row
     constexpr int BK = ROWB / EB;                 // K elements per tile
     constexpr int ACPR = BK / 4;                  // A float4 chunks per row
     constexpr int ACH = BM * ACPR / NT;           // A float4 chunks per thread (FP32 A)
@@ -252,7 +256,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
                 const int64_t n = n0 + row;
                 const int64_t kb = (int64_t)k0 * EB + kc * 16;
                 if (n < g.N && kb < KB) rb[p][i] = *reinterpret_cast<const uint4*>(Bp[p] + n * KB + kb);
@@ -297,7 +301,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+                const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
                 *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = rb[p][i];
             }
     };

@@ -153,7 +153,7 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         if (p->ch_frames > 0 && hipMalloc(&p->ws, p->ch_frames * p->W * sizeof(float)) != hipSuccess)
             return bail(TINA_ERR_OUT_OF_MEMORY, "plan: workspace allocation");
         if (p->ch_frames > 0 && form_scaled(form)) {
-            p->amax_parts_cap = p->W / 64 > 1 ? p->W / 64 : 1;
+            p->amax_parts_cap = p->W / 32 > 1 ? p->W / 32 : 1;  // the most parts: one per 32 lanes at VEC = 1
             if (hipMalloc(&p->amax, p->ch_frames * p->amax_parts_cap * sizeof(float)) != hipSuccess)
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: scale workspace allocation");
         }
