@@ -222,7 +222,7 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
         outs = [torch.empty((x.size // s.P, s.P), dtype=torch.complex64, device="cuda") for s, x in zip(specs, xs)]
         items = [(plans[s.P], x, o) for s, x, o in zip(specs, xd, outs)]
         b = Batch(prec, max_items=len(items), workspace_bytes=2 << 30)
-        tf, bpc = b.tune(items)
+        tf, tile_n = b.tune(items)
         for _ in range(2):
             b.execute(items)
         torch.cuda.synchronize()
@@ -234,7 +234,7 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
         flops = sum(dft_flops_per_frame(s.P, True) * (x.size // s.P) for s, x in zip(specs, xs))
         res[prec] = {"gsps": round(total / sec / 1e9, 3), "ms_per_batch": round(sec * 1e3, 3),
                      "dft_useful_tflops_incl_fir": round(flops / sec / 1e12, 2),
-                     "tuned": {"fir_frames_per_thread_mult": tf, "gemm_blocks_per_cu": bpc}}
+                     "tuned": {"fir_frames_per_thread_mult": tf, "gemm_tile_n": tile_n}}
         log(f"[bench] batched {prec}: {res[prec]}")
         b.close()
         del outs, items

@@ -63,7 +63,8 @@ tina_status tina_pfb_batch_destroy(tina_pfb_batch_t batch);
 tina_status tina_pfb_batch_execute(tina_pfb_batch_t batch, tina_pfb_work* items, int32_t n, void* stream);
 
 /* Autotune the launch shapes (frames per FIR thread as a multiple of the tap
- * ring, GEMM blocks per compute unit) on this batch's shape by timing each
+ * ring; GEMM tile columns, 128 or 256 -- 256 is tried for FP32) on this
+ * batch's shape by timing each
  * candidate on the device, without writing any state; the choice is cached
  * under a signature of the shape (precision, total samples rounded to a
  * power of two, distinct (P, M, sample type)) for later
@@ -72,7 +73,7 @@ tina_status tina_pfb_batch_execute(tina_pfb_batch_t batch, tina_pfb_work* items,
  * the items (repeatedly).  Synchronous.  The chosen values are returned
  * through the two pointers when they are not NULL. */
 tina_status tina_pfb_batch_tune(tina_pfb_batch_t batch, tina_pfb_work* items, int32_t n, void* stream,
-                                int32_t* fir_tf_mult, int32_t* gemm_blocks_per_cu);
+                                int32_t* fir_tf_mult, int32_t* gemm_tile_n);
 
 /* Host-only helper used to plan the persistent launches (exposed for
  * testing): split the units of one stage, given per item as units[i] units

@@ -33,7 +33,7 @@ namespace {
 
 struct Tune {
     int fir_tf_mult = 2;      // frames per FIR thread = mult * MT
-    int gemm_blocks_per_cu = 2;
+    int gemm_tile_n = kGemmBN;  // GEMM tile columns: kGemmBN, or 2 * kGemmBN (FP32 only)
 };
 
 std::mutex g_tune_mu;
@@ -51,7 +51,8 @@ void tune_load_locked() {
     if (!f) return;
     char key[512];
     int a, b;
-    while (fscanf(f, "%511s %d %d", key, &a, &b) == 3) g_tune_cache[key] = Tune{a, b};
+    while (fscanf(f, "%511s %d %d", key, &a, &b) == 3)
+        g_tune_cache[key] = Tune{a, (b == kGemmBN || b == 2 * kGemmBN) ? b : kGemmBN};
     fclose(f);
 }
 
@@ -60,7 +61,7 @@ void tune_store_locked() {
     if (!p) return;
     FILE* f = fopen(p, "w");
     if (!f) return;
-    for (const auto& kv : g_tune_cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.fir_tf_mult, kv.second.gemm_blocks_per_cu);
+    for (const auto& kv : g_tune_cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.fir_tf_mult, kv.second.gemm_tile_n);
     fclose(f);
 }
 
@@ -250,7 +251,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         const int64_t runs = (F + TF - 1) / TF;
         fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
         fc[i] = (double)TF * MT;
-        gu[i] = F > 0 ? ((F + kGemmBM - 1) / kGemmBM) * ((p->N + kGemmBN - 1) / kGemmBN) : 0;
+        gu[i] = F > 0 ? ((F + kGemmBM - 1) / kGemmBM) * ((p->N + tune.gemm_tile_n - 1) / tune.gemm_tile_n) : 0;
         gc[i] = (double)p->K;
         bi.fir_unit0 = f0;
         bi.gemm_unit0 = g0;
@@ -268,6 +269,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         }
         s0 += su[i];
     }
+    t->gemm_bn = tune.gemm_tile_n;
     t->fir_units = f0;
     t->gemm_units = g0;
     t->st_units = s0;
@@ -308,13 +310,12 @@ int64_t gemm_grid(const BatchTable* t) {
 
 tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
                           bool always, int64_t fixed_gemm_grid = 0) {
-    (void)tune;
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     if (always || b->h_table->fir_units > 0)
         HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), form_fir_qmode(b->form), grid_fir, s));
     if (always || b->h_table->gemm_units > 0)
-        HIP_TRY(launch_gemm_batch(b->d_table, b->form, form_fir_qmode(b->form) != 0, (int)grid_gemm, s));
+        HIP_TRY(launch_gemm_batch(b->d_table, b->form, form_fir_qmode(b->form) != 0, tune.gemm_tile_n, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }
@@ -337,7 +338,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
             // (a stage with no units returns at once), so one graph per kernel
             // variant serves every step.
             const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
-                                    std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_blocks_per_cu);
+                                    std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
             auto it = b->graphs.find(key);
             if (it == b->graphs.end()) {
                 hipGraph_t graph = nullptr;
@@ -501,7 +502,7 @@ tina_status tina_pfb_batch_execute(tina_pfb_batch_t b, tina_pfb_work* w, int32_t
 }
 
 tina_status tina_pfb_batch_tune(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n, void* stream,
-                                int32_t* fir_tf_mult, int32_t* gemm_blocks_per_cu) {
+                                int32_t* fir_tf_mult, int32_t* gemm_tile_n) {
     if (!b) return fail(TINA_ERR_INVALID_ARGUMENT, "batch_tune: NULL batch");
     std::vector<int64_t> frames;
     tina_status st = validate(b, w, n, frames);
@@ -512,12 +513,15 @@ tina_status tina_pfb_batch_tune(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n,
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int mults[] = {1, 2, 4};
-    const int bpcs[] = {1};  // the GEMM runs one block per tile; only the FIR shape is tuned
+    // 128 x 256 GEMM tiles halve the A re-reads and suit FP32's long K tiles;
+    // the other forms keep 128 x 128.
+    const int tile_ns[] = {kGemmBN, 2 * kGemmBN};
+    const int n_tiles = b->form == FORM_FP32 ? 2 : 1;
     Tune best;
     float best_ms = 1e30f;
     for (int m : mults)
-        for (int bpc : bpcs) {
-            Tune t{m, bpc};
+        for (int ti = 0; ti < n_tiles; ++ti) {
+            Tune t{m, tile_ns[ti]};
             st = run_batch(b, w, n, s, t, true, frames);  // warm-up, no state updates
             if (st != TINA_OK) break;
             HIP_TRY(hipEventRecord(e0, s));
@@ -541,7 +545,7 @@ tina_status tina_pfb_batch_tune(tina_pfb_batch_t b, tina_pfb_work* w, int32_t n,
         tune_store_locked();
     }
     if (fir_tf_mult) *fir_tf_mult = best.fir_tf_mult;
-    if (gemm_blocks_per_cu) *gemm_blocks_per_cu = best.gemm_blocks_per_cu;
+    if (gemm_tile_n) *gemm_tile_n = best.gemm_tile_n;
     return TINA_OK;
 }
 

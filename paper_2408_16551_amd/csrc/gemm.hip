@@ -538,9 +538,9 @@ __global__ __launch_bounds__(NT) void dft_gemm_raw_kernel(GemmArgs g) {
 // BatchTable); blocks past the end of their range return at once.  (A
 // persistent loop over tiles keeps per-tile state live across iterations and
 // halves the occupancy, so each block does one tile.)  RAW: A in operand form.
-template <int FORM, bool RAW>
+template <int FORM, bool RAW, int WN = kGemmBN / 64>
 __global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __restrict__ t) {
-    constexpr int WN = kGemmBN / 64, BN = kGemmBN;
+    constexpr int BN = 64 * WN;
     static_assert(kGemmBM == BM, "batch planner and kernel agree on the tile");
     using Smem = std::conditional_t<RAW, RawSmem<FORM, WN>, GemmSmem<FORM, WN>>;
     __shared__ __attribute__((aligned(16))) Smem sm;
@@ -579,8 +579,14 @@ hipError_t launch_raw(const GemmArgs& g, hipStream_t s) {
 
 bool gemm_raw_form(int form) { return form == FORM_MXFP8 || form == FORM_BF16 || form == FORM_BF16X3; }
 
-hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int grid, hipStream_t s) {
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s) {
     const dim3 gd(grid), bd(NT);
+    if (tile_n == 2 * kGemmBN) {
+        if (raw || form != FORM_FP32) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP32, false, 2 * kGemmBN / 64>), gd, bd, 0, s, t);
+        return hipGetLastError();
+    }
+    if (tile_n != kGemmBN) return hipErrorInvalidValue;
     if (raw) {
         switch (form) {
             case FORM_BF16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16, true>), gd, bd, 0, s, t); break;

@@ -143,6 +143,8 @@ struct BatchTable {
     int32_t pad_;
     int64_t fir_units, gemm_units, st_units;
     int64_t fir_bounds[9], gemm_bounds[9], st_bounds[9];
+    int32_t gemm_bn;        // GEMM tile columns of this launch (kGemmBN or 2 * kGemmBN)
+    int32_t pad2_;
     BatchItem items[1];     // n_items entries follow
 };
 
@@ -168,7 +170,9 @@ hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool
 inline int form_fir_qmode(int form) {
     return form == FORM_MXFP8 ? 1 : (form == FORM_BF16 ? 2 : (form == FORM_BF16X3 ? 3 : 0));
 }
-hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int grid, hipStream_t s);
+// tile_n: the table's GEMM tile columns (kGemmBN for every form; 2 * kGemmBN
+// also for FP32 with A in FP32).
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s);
 
 }  // namespace tina

@@ -353,7 +353,7 @@ class Batch:
         return [arr[i].frames_written for i in range(len(items))]
 
     def tune(self, items, stream=None):
-        """Autotune launch shapes on this batch shape; returns (fir_tf_mult, gemm_blocks_per_cu)."""
+        """Autotune launch shapes on this batch shape; returns (fir_tf_mult, gemm_tile_n)."""
         arr = self._works(items)
         a, b = ctypes.c_int32(), ctypes.c_int32()
         check(load().tina_pfb_batch_tune(self.handle, arr, len(items), _stream_handle(stream), ctypes.byref(a),

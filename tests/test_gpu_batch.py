@@ -128,8 +128,8 @@ def test_batch_tune_then_execute_bitwise():
     plans, xs, outs = _items(MIX[:5], "fp32", seed=11)
     xd = [torch.from_numpy(x).cuda() for x in xs]
     b = Batch("fp32", max_items=8)
-    tf, bpc = b.tune([(p, x, o) for p, x, o in zip(plans, xd, outs)])
-    assert tf in (1, 2, 4) and bpc in (1, 2)
+    tf, tile_n = b.tune([(p, x, o) for p, x, o in zip(plans, xd, outs)])
+    assert tf in (1, 2, 4) and tile_n in (128, 256)
     fw = b.execute([(p, x, o) for p, x, o in zip(plans, xd, outs)])
     torch.cuda.synchronize()
     for p, x, o, f in zip(plans, xd, outs, fw):
