@@ -133,8 +133,17 @@ typedef struct tina_pfb_desc {
  *                      P1, twiddles, P1 DFTs of size P2, each size-P1/P2 DFT a
  *                      small matrix product on the MFMA units in FP32 -- 8 P (P1 + P2)
  *                      flops per frame instead of 8 P^2.  FP32 only; 256 <= P <= 4096;
- *                      single-stream execute only (not in batches or a server). */
-typedef enum tina_dft_algorithm { TINA_DFT_DENSE = 0, TINA_DFT_FACTORED = 1 } tina_dft_algorithm;
+ *                      single-stream execute only (not in batches or a server).
+ *   TINA_DFT_FUSED     the dense product with the polyphase FIR fused into it:
+ *                      each matrix-product tile forms its rows of FIR output
+ *                      from the input stream in on-chip memory (a sliding
+ *                      window over the frames staged in LDS), so the FIR output
+ *                      never goes to HBM.  Results are bit for bit those of
+ *                      TINA_DFT_DENSE.  FP32, taps <= 16, single-stream
+ *                      execute; a call whose input is not 16-byte aligned (or
+ *                      whose residue leaves the history a partial float4) runs
+ *                      the two-kernel path instead. */
+typedef enum tina_dft_algorithm { TINA_DFT_DENSE = 0, TINA_DFT_FACTORED = 1, TINA_DFT_FUSED = 2 } tina_dft_algorithm;
 
 typedef struct tina_pfb_plan_s* tina_pfb_plan_t;
 typedef struct tina_pfb_state_s* tina_pfb_state_t;

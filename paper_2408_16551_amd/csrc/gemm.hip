@@ -355,6 +355,164 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, s_sc);
 }
 
+// FIR fused into the FP32 GEMM: the A tile of K tile t (frames m0.., K
+// columns k0..k0+BK) is computed in the tile from the input stream instead of
+// being read from a workspace the FIR kernel wrote.  The BM + M - 1 input
+// rows it needs (frame f of the tile reads frames f - M + 1..f) and the taps
+// of its columns are staged in LDS with the B tile; then every thread forms
+// its A chunks with the FIR kernel's FMA order (tap 0 times the newest frame,
+// then fused multiply-adds for m = 1..M-1), so A -- and the output -- are bit
+// for bit those of the two-kernel path.  MT: the largest M (compile time);
+// EXACT: M == MT.
+struct FusedArgs {
+    GemmArgs g;   // g.A unused
+    FirArgs x;    // input stream, taps, frame numbering (x.y unused)
+};
+
+template <int WN, int MT>
+struct FusedSmem {
+    static constexpr int BN = 64 * WN, BK = ROWB / 4, XR = BM + MT - 1;
+    uint8_t tiles[(BM + BN) * RS];  // A (BM rows), then B (BN rows), RS bytes a row
+    float4 xs[XR * (BK / 4)];       // input rows of the K tile, BK floats each (no pad: 16 lanes read 2 rows)
+    float ts[MT * BK];              // taps of the K tile's columns, tap m at ts[m * BK + column]
+};
+
+template <int WN, int MT, bool EXACT>
+__device__ __forceinline__ void gemm_tile_fused(const FusedArgs& fa, int64_t m0, int64_t n0, FusedSmem<WN, MT>& sm) {
+    constexpr int FORM = FORM_FP32;
+    constexpr int BN = 64 * WN, WC = 32 * WN;
+    constexpr int BK = ROWB / 4, K4 = BK / 4;           // K floats per tile, float4 chunks per row
+    constexpr int XR = BM + MT - 1;                      // input rows staged per K tile
+    constexpr int XCH = (XR * K4 + NT - 1) / NT;         // input float4 chunks per thread
+    constexpr int TCH = (MT * BK + NT - 1) / NT;         // taps per thread
+    constexpr int ACH = BM * K4 / NT;                    // A chunks per thread
+    constexpr int BCH = BN * (ROWB / 16) / NT;
+    constexpr int NSLAB = ROWB / FT<FORM>::SLAB, SLAB = FT<FORM>::SLAB, RD = 1;
+    const GemmArgs& g = fa.g;
+    const FirArgs& a = fa.x;
+    const int M = EXACT ? MT : a.M;
+
+    uint8_t* As = sm.tiles;
+    uint8_t* Bs = sm.tiles + BM * RS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 31, lh = lane >> 5;
+    const int64_t KB = (int64_t)g.K * 4;
+    const int64_t x0 = m0 - (M - 1);  // frame of staged row 0 (may be negative: history)
+
+    float4 rx[XCH];
+    float rt[TCH];
+    uint4 rb[BCH];
+    auto load_tile = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < XCH; ++i) {
+            const int c = tid + i * NT, j = c / K4, k4 = c % K4;
+            const int64_t f = x0 + j;  // frame of this row
+            rx[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < BM + M - 1 && f < g.F) {
+                const int64_t e = (a.g0 + f + a.M - 1) * (int64_t)a.W + k0 + 4 * k4;  // float in prefix ++ chunk
+                const float* p = e >= a.plen ? a.chunk + (e - a.plen) : a.prefix + e;
+                if (e >= a.plen || a.prefix) rx[i] = *reinterpret_cast<const float4*>(p);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TCH; ++i) {
+            const int c = tid + i * NT, m = c / BK, kk = c % BK;
+            rt[i] = (c < MT * BK && (EXACT || m < M)) ? a.taps[(int64_t)(M - 1 - m) * a.P + (k0 + kk) / a.cf] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < BCH; ++i) {
+            const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+            const int64_t n = n0 + row, kb = (int64_t)k0 * 4 + kc * 16;
+            rb[i] = (n < g.N && kb < KB) ? *reinterpret_cast<const uint4*>((const uint8_t*)g.B0 + n * KB + kb)
+                                         : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    // Stage the loaded tile, then form A in LDS.  Contains a barrier: called
+    // by every thread at the same point.
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int i = 0; i < XCH; ++i) {
+            const int c = tid + i * NT;
+            if (c < XR * K4) sm.xs[c] = rx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < TCH; ++i) {
+            const int c = tid + i * NT;
+            if (c < MT * BK) sm.ts[c] = rt[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BCH; ++i) {
+            const int c = tid + i * NT, row = c >> 3, kc = c & 7;
+            *reinterpret_cast<uint4*>(Bs + row * RS + kc * 16) = rb[i];
+        }
+        __syncthreads();
+        // A thread's ACH chunks share its column group k4 = tid % K4 (NT is a
+        // multiple of K4), so they share the taps; rows r = tid / K4 + i NT / K4.
+        const int k4 = tid % K4, r0 = tid / K4;
+        const float4* xr = sm.xs + (r0 + M - 1) * K4 + k4;  // staged row of frame m0 + r0
+        float4 fa4[ACH];
+        {
+            const float4 t = *reinterpret_cast<const float4*>(sm.ts + 4 * k4);
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) {
+                const float4 v = xr[i * (NT / K4) * K4];
+                fa4[i] = make_float4(t.x * v.x, t.y * v.y, t.z * v.z, t.w * v.w);
+            }
+        }
+#pragma unroll 2
+        for (int m = 1; m < (EXACT ? MT : M); ++m) {
+            const float4 t = *reinterpret_cast<const float4*>(sm.ts + m * BK + 4 * k4);
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) {
+                const float4 v = xr[i * (NT / K4) * K4 - m * K4];
+                fa4[i].x = fmaf(t.x, v.x, fa4[i].x);
+                fa4[i].y = fmaf(t.y, v.y, fa4[i].y);
+                fa4[i].z = fmaf(t.z, v.z, fa4[i].z);
+                fa4[i].w = fmaf(t.w, v.w, fa4[i].w);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ACH; ++i)
+            *reinterpret_cast<float4*>(As + (r0 + i * (NT / K4)) * RS + k4 * 16) = fa4[i];
+    };
+
+    f32x16 acc[2][WN], acc2[2][WN];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    __syncthreads();  // the previous tile of a persistent block is done with LDS
+    const int nk = (g.K + BK - 1) / BK;
+    load_tile(0);
+    store_tile();
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        if (t + 1 < nk) load_tile((t + 1) * BK);
+#pragma unroll
+        for (int s = 0; s < NSLAB; ++s) {
+            uint4 af[2][1][RD], bf[WN][1][RD];
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+                af[bm][0][0] = *reinterpret_cast<const uint4*>(As + (wm * 64 + bm * 32 + lr) * RS + s * SLAB + lh * 16);
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn)
+                bf[bn][0][0] = *reinterpret_cast<const uint4*>(Bs + (wn * WC + bn * 32 + lr) * RS + s * SLAB + lh * 16);
+            const int sa[2] = {0, 0}, sb[WN] = {};
+            mfma_slab<FORM, 1, RD, WN>(af, bf, acc, acc2, sa, sb);
+        }
+        __syncthreads();
+        if (t + 1 < nk) {
+            store_tile();
+            __syncthreads();
+        }
+    }
+    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, nullptr);
+}
+
 // Raw-operand tile: A arrives in the operand form (NP pieces of EB-byte
 // elements, K contiguous, row stride g.lda elements; block-scaled FP8 also
 // with a scale byte per 32 K), so a K tile of A is copied to LDS like B, with
@@ -533,6 +691,16 @@ __global__ __launch_bounds__(NT) void dft_gemm_raw_kernel(GemmArgs g) {
     gemm_tile_raw<FORM, WN>(g, m0, n0, sm);
 }
 
+template <int WN, int MT, bool EXACT>
+__global__ __launch_bounds__(NT, 2) void dft_gemm_fused_kernel(FusedArgs fa) {
+    constexpr int BN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) FusedSmem<WN, MT> sm;
+    const int64_t nm = (fa.g.F + BM - 1) / BM, nn = (fa.g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, BN, m0, n0);
+    gemm_tile_fused<WN, MT, EXACT>(fa, m0, n0, sm);
+}
+
 // Batched GEMM, one block per tile of any item: block b serves tile
 // i = b / 8 of XCD x = b % 8's contiguous, cost-balanced range of tiles (see
 // BatchTable); blocks past the end of their range return at once.  (A
@@ -606,6 +774,32 @@ hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool fused_supported(const FirArgs& x, int form) {
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    return form == FORM_FP32 && x.M >= 1 && x.M <= 16 && x.W % 32 == 0 && x.plen % 4 == 0 && al16(x.chunk) &&
+           (x.prefix == nullptr || al16(x.prefix));
+}
+
+hipError_t launch_dft_fused(const GemmArgs& g, const FirArgs& x, hipStream_t s) {
+    if (g.F <= 0) return hipSuccess;
+    if (!fused_supported(x, g.form)) return hipErrorInvalidValue;
+    FusedArgs fa;
+    fa.g = g;
+    fa.x = x;
+    constexpr int WN = 4, BN = 64 * WN;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    const dim3 grid((unsigned)(nm * nn)), block(NT);
+    auto go = [&](auto mt_tag) {
+        constexpr int MT = decltype(mt_tag)::value;
+        if (x.M == MT) hipLaunchKernelGGL((dft_gemm_fused_kernel<WN, MT, true>), grid, block, 0, s, fa);
+        else hipLaunchKernelGGL((dft_gemm_fused_kernel<WN, MT, false>), grid, block, 0, s, fa);
+        return hipGetLastError();
+    };
+    if (x.M <= 4) return go(std::integral_constant<int, 4>{});
+    if (x.M <= 8) return go(std::integral_constant<int, 8>{});
+    return go(std::integral_constant<int, 16>{});
 }
 
 hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {

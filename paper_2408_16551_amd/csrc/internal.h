@@ -101,6 +101,12 @@ struct GemmArgs {
     const uint8_t* Aqs;
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
+// The FIR fused into the FP32 GEMM (g.A unused; x describes the input stream
+// and taps as for launch_fir, x.y unused).  fused_supported: FP32, M <= 16,
+// W a multiple of 32, 16-byte aligned input with the prefix a whole number of
+// float4s.
+bool fused_supported(const FirArgs& x, int form);
+hipError_t launch_dft_fused(const GemmArgs& g, const FirArgs& x, hipStream_t s);
 // Forms whose A the FIR can write in operand form.
 bool gemm_raw_form(int form);
 

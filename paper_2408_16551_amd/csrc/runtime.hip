@@ -43,7 +43,7 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
     const int64_t ws_req = d->struct_size >= offsetof(tina_pfb_desc, dft_algorithm) ? d->workspace_bytes : 0;
     const int dft_alg = d->struct_size >= offsetof(tina_pfb_desc, reserved_) ? d->dft_algorithm : TINA_DFT_DENSE;
-    if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED)
+    if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED && dft_alg != TINA_DFT_FUSED)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown dft_algorithm");
     if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
@@ -66,6 +66,9 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     if (d->output == TINA_OUT_PFB && d->precision == TINA_PREC_MXFP8 &&
         (int64_t)d->channels * (d->sample_type == TINA_SAMPLE_C64 ? 2 : 1) % 128 != 0)
         return fail(TINA_ERR_UNSUPPORTED, "plan: MXFP8 needs 128 | channels (real) or 64 | channels (complex)");
+    if (dft_alg == TINA_DFT_FUSED && d->output == TINA_OUT_PFB &&
+        (d->precision != TINA_PREC_FP32 || d->taps > 16 || (int64_t)d->channels * (d->sample_type == TINA_SAMPLE_C64 ? 2 : 1) % 32 != 0))
+        return fail(TINA_ERR_UNSUPPORTED, "plan: the fused FIR + DFT needs FP32, taps <= 16 and 32 | channels * floats per sample");
     if (dft_alg == TINA_DFT_FACTORED && d->output == TINA_OUT_PFB &&
         (d->precision != TINA_PREC_FP32 || !fft_supported(d->channels)))
         return fail(TINA_ERR_UNSUPPORTED, "plan: the factored DFT needs FP32 and 256 <= channels <= 4096");
@@ -270,6 +273,19 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
                 fa.ldq = p->W;
                 if (form_mx(form)) fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
                 if (form == TINA_PREC_BF16X3) fa.q1 = (uint8_t*)p->ws + (int64_t)p->ch_frames * p->W * 2;
+            }
+            if (p->dft_algorithm == TINA_DFT_FUSED && fused_supported(fa, form)) {
+                GemmArgs ga{};
+                ga.B0 = p->B[0];
+                ga.out = (float*)d_out + c0 * ldo;
+                ga.ldo = ldo;
+                ga.F = Fc;
+                ga.K = p->K;
+                ga.N = p->N;
+                ga.real_pack = p->cf == 1;
+                ga.form = form;
+                HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_fused(ga, fa, s); }));
+                continue;
             }
             HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
             if (p->dft_algorithm == TINA_DFT_FACTORED) {
