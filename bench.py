@@ -241,25 +241,33 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
     return res
 
 
-def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005):
+def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005, device=False,
+                  frames_per_step=1024):
     """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
     1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
     random stream, length log-uniform 2^16-2^22.  The rate is rho times the
     capacity measured with a closed burst.  Latency = done - scheduled arrival,
-    including the host-to-device and device-to-host copies."""
+    including the host-to-device and device-to-host copies (device=True:
+    requests already in HBM, used in place, no copies)."""
     import threading
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Server
     streams = workloads.serving_streams(seed)
     sv = Server(precision, max_streams=len(streams), max_active=32, hbm_budget_bytes=budget_bytes,
-                frames_per_step=256, use_graph=True, max_channels=4096)
+                frames_per_step=frames_per_step, use_graph=True, max_channels=4096)
     sids = [sv.stream(s.P, s.M, "c64") for s in streams]
     g = np.random.Generator(np.random.PCG64(seed + 7))
     max_len = 1 << 22
     pool = torch.empty(max_len * 8, dtype=torch.complex64, pin_memory=True).numpy()
     pool[:] = workloads.random_tone_stream(g, pool.size, 4)
     n_out = 64   # output buffers in flight (frames * P <= residue + n < max_len + 4096)
-    out_pool = [torch.empty(max_len + 4096, dtype=torch.complex64, pin_memory=True).numpy() for _ in range(n_out)]
+    if device:
+        pool = torch.from_numpy(pool).cuda()
+        out_pool = [torch.empty(max_len + 4096, dtype=torch.complex64, device="cuda") for _ in range(n_out)]
+        torch.cuda.synchronize()
+    else:
+        out_pool = [torch.empty(max_len + 4096, dtype=torch.complex64, pin_memory=True).numpy() for _ in range(n_out)]
+    size = pool.numel() if device else pool.size
     free_out = list(range(n_out))
     lock = threading.Condition()
     residues = [0] * len(streams)
@@ -268,19 +276,23 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
         P = streams[sid].P
         frames = (residues[sid] + n) // P
         residues[sid] = (residues[sid] + n) % P
-        off = int(g.integers(0, pool.size - n + 1))
+        off = int(g.integers(0, size - n + 1))
         return pool[off: off + n], frames
 
     def lens(k):
         return np.floor(2.0 ** g.uniform(16.0, 22.0, size=k)).astype(np.int64)
 
-    # closed-loop capacity: a burst of 64 requests
+    # closed-loop capacity: a burst of 256 requests (at most n_out outputs in flight)
     burst = []
-    L = lens(64)
+    L = lens(256)
     t0 = time.perf_counter()
     for i, n in enumerate(L):
         sid = i % len(streams)
         x, frames = make(i, sid, int(n))
+        if not free_out:  # recycle the oldest output buffer
+            rid0, oi0 = burst.pop(0)
+            sv.wait(rid0)
+            free_out.append(oi0)
         oi = free_out.pop()
         out = out_pool[oi][: frames * streams[sid].P].reshape(frames, streams[sid].P)
         burst.append((sv.submit(sids[sid], x, out), oi))
@@ -335,6 +347,8 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     sv.close()
     m = np.array(lat[n_warm:], dtype=np.float64)
     return {"precision": precision, "hbm_budget_bytes": budget_bytes, "rho": rho,
+            "buffers": "device (in place)" if device else "host (pinned; copied in and out)",
+            "frames_per_step": frames_per_step,
             "capacity_gsps_closed_burst": round(cap / 1e9, 3), "rate_req_per_s": round(lam, 1),
             "mean_request_samples": round(mean_len), "requests_measured": n_meas, "warmup_requests": n_warm,
             "p50_ms": round(float(np.percentile(m, 50)), 3), "p99_ms": round(float(np.percentile(m, 99)), 3),
@@ -445,6 +459,7 @@ def main():
         log("[bench] serving workload")
         result["serving"] = [serving_bench(torch, prec, bud) for prec in ("fp8", "bf16x3")
                              for bud in (8 << 30, 256 << 20)]
+        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True) for prec in ("fp8", "bf16x3")]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")

@@ -70,11 +70,17 @@ tina_status tina_server_stream_create(tina_server_t server, int32_t channels, in
  * host_in (host memory; pinned memory makes the copy asynchronous), the
  * output rows written to host_out (host memory, room for
  * out_capacity_frames rows of the stream's output, layout as
- * tina_pfb_execute).  Both host buffers are lent to the server until the
- * request is reported done. */
+ * tina_pfb_execute).  Both buffers are lent to the server until the request
+ * is reported done.
+ *
+ * flags: TINA_REQ_DEVICE_BUFFERS -- host_in and host_out are device memory
+ * on the server's device (the caller's; 4-byte aligned input, 8-byte aligned
+ * output): the steps read and write them in place, no copy is made and the
+ * arena (hbm_budget_bytes) is not used, so admission waits only for a slot. */
+#define TINA_REQ_DEVICE_BUFFERS 1
 typedef struct tina_request {
     int32_t stream_id;
-    int32_t pad_;
+    int32_t flags;             /* 0 or TINA_REQ_DEVICE_BUFFERS */
     const void* host_in;
     int64_t n_samples;
     void* host_out;

@@ -190,15 +190,19 @@ void tina_server_s::loop() {
                 LStream& ls = streams[q->r.stream_id];
                 if (ls.busy || ls.queued.empty() || ls.queued.front() != q->id) { ++it; continue; }
                 if ((int)active.size() >= cfg.max_active) break;
-                const int64_t oi = arena.alloc(q->in_bytes);
-                const int64_t oo = oi >= 0 ? arena.alloc(q->out_bytes) : -1;
-                if (oi < 0 || oo < 0) {
-                    if (oi >= 0) arena.release(oi);
-                    ++stats.admission_waits;
-                    break;
+                if (!(q->r.flags & TINA_REQ_DEVICE_BUFFERS)) {
+                    const int64_t oi = arena.alloc(q->in_bytes);
+                    const int64_t oo = oi >= 0 ? arena.alloc(q->out_bytes) : -1;
+                    if (oi < 0 || oo < 0) {
+                        if (oi >= 0) arena.release(oi);
+                        ++stats.admission_waits;
+                        break;
+                    }
+                    q->off_in = oi;
+                    q->off_out = oo;
+                } else {
+                    q->in_ready = true;  // already on the device
                 }
-                q->off_in = oi;
-                q->off_out = oo;
                 q->phase = ACTIVE;
                 q->res.t_admit_us = now_us();
                 ls.busy = true;
@@ -212,6 +216,7 @@ void tina_server_s::loop() {
             stats.arena_high_water = arena.high();
         }
         for (Req* q : admitted) {  // input copies, outside the lock
+            if (q->r.flags & TINA_REQ_DEVICE_BUFFERS) continue;
             if (q->in_bytes > 0 && q->r.n_samples > 0)
                 (void)hipMemcpyAsync(arena_base + q->off_in, q->r.host_in, q->r.n_samples * q->sample_bytes,
                                      hipMemcpyHostToDevice, s_h2d);
@@ -235,9 +240,12 @@ void tina_server_s::loop() {
                 tina_pfb_work w{};
                 w.plan = ls.plan;
                 w.state = ls.state;
-                w.d_in = arena_base + q->off_in + q->samples_done * q->sample_bytes;
+                const bool dev = (q->r.flags & TINA_REQ_DEVICE_BUFFERS) != 0;
+                const uint8_t* in0 = dev ? (const uint8_t*)q->r.host_in : arena_base + q->off_in;
+                uint8_t* out0 = dev ? (uint8_t*)q->r.host_out : arena_base + q->off_out;
+                w.d_in = in0 + q->samples_done * q->sample_bytes;
                 w.n_samples = s;
-                w.d_out = arena_base + q->off_out + q->frames_done * q->row_bytes;
+                w.d_out = out0 + q->frames_done * q->row_bytes;
                 w.out_capacity_frames = q->frames_total - q->frames_done;
                 items.push_back(w);
                 in_step.push_back(q);
@@ -281,7 +289,9 @@ void tina_server_s::loop() {
                 Req* q = *it;
                 const bool empty = std::find(empty_done.begin(), empty_done.end(), q) != empty_done.end();
                 if (!empty && (q->samples_done < q->r.n_samples || !q->in_ready)) { ++it; continue; }
-                if (q->frames_done > 0)
+                // Device buffers: the step that wrote the last rows has been
+                // waited for, so only host outputs need a copy.
+                if (q->frames_done > 0 && !(q->r.flags & TINA_REQ_DEVICE_BUFFERS))
                     (void)hipMemcpyAsync(q->r.host_out, arena_base + q->off_out, q->frames_done * q->row_bytes,
                                          hipMemcpyDeviceToHost, s_d2h);
                 (void)hipEventRecord(q->ev_out, s_d2h);
@@ -427,6 +437,10 @@ tina_status tina_pfb_submit(tina_server_t sv, const tina_request* r, uint64_t* i
     if (sv->stop) return fail(TINA_ERR_CANCELLED, "submit: server is stopping");
     if (r->stream_id < 0 || r->stream_id >= (int)sv->streams.size()) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad stream id");
     if (r->n_samples < 0 || (r->n_samples > 0 && !r->host_in)) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad input");
+    if (r->flags & ~TINA_REQ_DEVICE_BUFFERS) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: unknown flags");
+    const bool dev = (r->flags & TINA_REQ_DEVICE_BUFFERS) != 0;
+    if (dev && (((uintptr_t)r->host_in & 3) || ((uintptr_t)r->host_out & 7)))
+        return fail(TINA_ERR_INVALID_ARGUMENT, "submit: device buffers misaligned");
     LStream& ls = sv->streams[r->stream_id];
     const tina_pfb_plan_s* p = ls.plan;
     const int64_t frames = (ls.submitted_residue + r->n_samples) / p->P;
@@ -439,8 +453,8 @@ tina_status tina_pfb_submit(tina_server_t sv, const tina_request* r, uint64_t* i
     q->sample_bytes = p->cf * 4;
     q->row_bytes = p->kout * 8;
     q->frames_total = frames;
-    q->in_bytes = r->n_samples * q->sample_bytes;
-    q->out_bytes = frames * q->row_bytes;
+    q->in_bytes = dev ? 0 : r->n_samples * q->sample_bytes;  // arena bytes (none for device buffers)
+    q->out_bytes = dev ? 0 : frames * q->row_bytes;
     if (Arena::round(q->in_bytes) + Arena::round(q->out_bytes) > sv->arena.capacity()) {
         delete q;
         return fail(TINA_ERR_TOO_LARGE, "submit: request buffers exceed the HBM budget");

@@ -58,7 +58,7 @@ class _ServerConfig(ctypes.Structure):
 
 
 class _Request(ctypes.Structure):
-    _fields_ = [("stream_id", ctypes.c_int32), ("pad_", ctypes.c_int32), ("host_in", ctypes.c_void_p),
+    _fields_ = [("stream_id", ctypes.c_int32), ("flags", ctypes.c_int32), ("host_in", ctypes.c_void_p),
                 ("n_samples", ctypes.c_int64), ("host_out", ctypes.c_void_p),
                 ("out_capacity_frames", ctypes.c_int64)]
 
@@ -424,15 +424,24 @@ class Server:
         P, st = self._streams[sid]
         return P if st == "c64" else P // 2 + 1
 
-    def submit(self, sid: int, x: np.ndarray, out: np.ndarray) -> int:
-        """Queue x (host array, float32 or complex64) for stream sid; the output
-        rows go to out (host complex64 array, frames x channels).  Both arrays
-        are held until the request is collected."""
+    def submit(self, sid: int, x, out) -> int:
+        """Queue x (float32 or complex64) for stream sid; the output rows go to
+        out (complex64, frames x channels).  Host numpy arrays are copied in and
+        out by the server; CUDA tensors (both) are used in place on the device
+        (TINA_REQ_DEVICE_BUFFERS).  Both are held until the request is collected."""
         r = _Request()
         r.stream_id = int(sid)
-        r.host_in = x.ctypes.data if x.size else None
-        r.n_samples = x.size
-        r.host_out = out.ctypes.data if out.size else None
+        if hasattr(x, "is_cuda"):
+            if not (x.is_cuda and getattr(out, "is_cuda", False) and x.is_contiguous() and out.is_contiguous()):
+                raise ValueError("device requests need contiguous CUDA tensors for input and output")
+            r.flags = 1
+            r.host_in = x.data_ptr() if x.numel() else None
+            r.n_samples = x.numel()
+            r.host_out = out.data_ptr() if out.numel() else None
+        else:
+            r.host_in = x.ctypes.data if x.size else None
+            r.n_samples = x.size
+            r.host_out = out.ctypes.data if out.size else None
         r.out_capacity_frames = out.shape[0] if out.ndim == 2 else 0
         rid = ctypes.c_uint64()
         check(load().tina_pfb_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))

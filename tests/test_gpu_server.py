@@ -155,3 +155,54 @@ def test_server_rejects_too_large_and_cancels():
     else:
         assert sv.wait(ids[-1], timeout_s=60)["status"] == 0
     sv.close()
+
+
+def test_server_device_buffers_equal_one_shot_bitwise():
+    # TINA_REQ_DEVICE_BUFFERS: CUDA tensors in and out, used in place; mixed
+    # with host requests on other streams.
+    from paper_2408_16551_amd.pfb import Server
+    reqs = _workload(23, n_req=20)
+    ref = _one_shot(reqs, "fp32")
+    sv = Server("fp32", max_streams=len(STREAMS), max_active=8, hbm_budget_bytes=1 << 30, frames_per_step=64,
+                use_graph=True, max_channels=1024)
+    sids = [sv.stream(P, M, "c64" if c else "r32") for P, M, c in STREAMS]
+    res = [0] * len(STREAMS)
+    pending = []
+    for s, x in reqs:
+        P = STREAMS[s][0]
+        frames = (res[s] + x.size) // P
+        res[s] = (res[s] + x.size) % P
+        if s % 2 == 0:  # device buffers
+            xd = torch.from_numpy(x).cuda()
+            out = torch.full((frames, sv.out_rows(sids[s])), float("nan"), dtype=torch.complex64, device="cuda")
+            torch.cuda.synchronize()
+            pending.append((s, sv.submit(sids[s], xd, out), out))
+        else:
+            out = np.full((frames, sv.out_rows(sids[s])), np.nan, dtype=np.complex64)
+            pending.append((s, sv.submit(sids[s], x, out), out))
+    outs = [[] for _ in STREAMS]
+    for s, rid, out in pending:
+        r = sv.wait(rid, timeout_s=60)
+        assert r["status"] == 0 and r["frames"] == out.shape[0]
+        outs[s].append(out.cpu().numpy() if hasattr(out, "is_cuda") else out)
+    st = sv.stats()
+    sv.close()
+    for s, r in enumerate(ref):
+        if r is None:
+            continue
+        assert np.array_equal(np.concatenate(outs[s]), r)
+    assert st["completed"] == len(reqs)
+
+
+def test_server_device_request_checks():
+    from paper_2408_16551_amd.pfb import Server, TinaError
+    sv = Server("fp32", max_streams=1, max_active=2, hbm_budget_bytes=1 << 26, frames_per_step=64,
+                use_graph=False, max_channels=256)
+    sid = sv.stream(256, 8, "r32")
+    x = torch.zeros(256 * 4, device="cuda")
+    with pytest.raises(ValueError):  # the binding refuses a host output with a device input
+        sv.submit(sid, x, np.zeros((4, 129), dtype=np.complex64))
+    out = torch.zeros((4 * 129 + 1,), dtype=torch.complex64, device="cuda")[1:].view(4, 129)  # offset views are fine
+    rid = sv.submit(sid, x, out)
+    assert sv.wait(rid, timeout_s=30)["status"] == 0
+    sv.close()
