@@ -371,8 +371,9 @@ def main():
                     help="run only a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
-                 "(--gpus must be 1); see DESIGN.md for how the filter bank would shard.")
+        sys.exit("bench.py measures one GPU only: the library has no multi-GPU path (--gpus must be 1); "
+                 "independent streams would be placed whole on GPUs, one long stream split by time with a "
+                 "(M-1)*P-sample halo per boundary.")
 
     import torch
 

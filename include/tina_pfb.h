@@ -39,7 +39,7 @@ extern "C" {
 typedef enum tina_status {
     TINA_OK = 0,
     TINA_ERR_INVALID_ARGUMENT = 1, /* a NULL handle/pointer, a bad size or alignment */
-    TINA_ERR_UNSUPPORTED = 2,      /* valid request this build does not implement */
+    TINA_ERR_UNSUPPORTED = 2,      /* valid request the library does not implement */
     TINA_ERR_OUT_OF_MEMORY = 3,    /* a device or host allocation failed */
     TINA_ERR_DEVICE = 4,           /* a HIP runtime call failed */
     TINA_ERR_BUSY = 5,             /* a queue is full; retry later */

@@ -135,3 +135,15 @@ def test_server_config_validated_before_device(lib):
     r = pfb._Request()
     rid = ctypes.c_uint64()
     assert lib.tina_pfb_submit(None, ctypes.byref(r), ctypes.byref(rid)) == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # The build runs on one GPU; --gpus N > 1 must exit with a message, before
+    # touching any device.
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0
+    assert "--gpus must be 1" in (r.stdout + r.stderr)
