@@ -361,8 +361,8 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged batched workload")
@@ -435,7 +435,7 @@ def main():
         from oracle import Oracle
         o = Oracle()
         forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8", "mxfp8", "fp32/factored"]
-        result["forms"] = {w.name: forms_table(w, forms, max(5, args.steps // 2), 2, torch, o, 24)}
+        result["forms"] = {w.name: forms_table(w, forms, 20, 5, torch, o, 24)}
         del xd
         wd = workloads.wide_dynamic_range()
         result["forms"][wd.name] = forms_table(wd, forms, 5, 2, torch, o, 12)
