@@ -48,7 +48,7 @@ constexpr int BM = 128;               // block tile rows (frames); columns BN = 
 constexpr int ROWB = 128;             // bytes of each operand row per K tile
 constexpr int RS = ROWB + 16;         // LDS row stride: 16-byte pad keeps 16-byte reads conflict-free
 constexpr int NT = 256;               // threads per block
-constexpr int GROUP_M = 8;            // m-tiles swept per column of n-tiles
+constexpr int GROUP_M = 16;           // m-tiles swept per column of n-tiles
 
 // Per-frame scale 2^e with the frame's largest |y| * 2^-e <= limit.
 __device__ inline int frame_exponent(float amax, float limit) {
@@ -174,27 +174,46 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 31, lh = lane >> 5;
     const float corr = (FORM == FORM_FP16X3) ? (1.0f / 2048.0f) : 1.0f;
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
+    // Element v of block (bm, bn) sits at row rb + bm * 32 + 8 * (v >> 2) +
+    // (v & 3) of the lane's column: its offset from the lane's first row is a
+    // wave-uniform multiple of ldo.  Tiles with every row present skip the row
+    // test; the zero imaginary parts of X_0 and X_{P/2} are written apart.
+    const int64_t rb = m0 + wm * 64 + 4 * lh;
+    float* const obase = g.out + rb * g.ldo;
+    auto store_rows = [&](auto check_rows) {
+        constexpr bool CHECK = decltype(check_rows)::value;
 #pragma unroll
         for (int bn = 0; bn < WN; ++bn) {
             const int64_t col = n0 + wn * WC + bn * 32 + lr;
             if (col >= g.N) continue;
             int64_t oc = col;
             if (g.real_pack) oc = col >= 2 ? col : (col == 0 ? 0 : (int64_t)g.N);
+            float* const ocol = obase + oc;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int rloc = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3);
-                const int64_t row = m0 + rloc;
-                if (row >= g.F) continue;
-                float val = acc[bm][bn][v];
-                if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
-                if constexpr (ft::SCALED) val *= s_sc[rloc];
-                float* o = g.out + row * g.ldo;
-                o[oc] = val;
-                if (g.real_pack && col < 2) o[oc + 1] = 0.0f;  // Im X_0, Im X_{P/2}
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int rr = bm * 32 + 8 * (v >> 2) + (v & 3);  // row offset from rb
+                    if (CHECK && rb + rr >= g.F) continue;
+                    float val = acc[bm][bn][v];
+                    if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
+                    if constexpr (ft::SCALED) val *= s_sc[wm * 64 + 4 * lh + rr];
+                    ocol[(int64_t)rr * g.ldo] = val;
+                }
+            if (g.real_pack && col < 2) {  // Im X_0, Im X_{P/2}
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int rr = bm * 32 + 8 * (v >> 2) + (v & 3);
+                        if (CHECK && rb + rr >= g.F) continue;
+                        ocol[(int64_t)rr * g.ldo + 1] = 0.0f;
+                    }
             }
         }
+    };
+    if (m0 + BM <= g.F) store_rows(std::false_type{});
+    else store_rows(std::true_type{});
 }
 
 
