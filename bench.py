@@ -98,6 +98,26 @@ def sampled_frames(F, M, n, seed):
     return np.array(sorted(fr), dtype=np.int64)
 
 
+def channel_errors(got, ref, w, fr):
+    """Relative L2 error of each channel over the sampled frames past the
+    warm-up: the worst channel, and the channel of the weakest tone placed at
+    a channel centre (the error a strong tone leaves on a faint one)."""
+    keep = fr >= w.M - 1
+    g = np.asarray(got, dtype=np.complex128)[keep]
+    r = np.asarray(ref, dtype=np.complex128)[keep]
+    num = np.sqrt((np.abs(g - r) ** 2).sum(axis=0))
+    den = np.sqrt((np.abs(r) ** 2).sum(axis=0))
+    ratio = num / np.maximum(den, np.finfo(np.float64).tiny)
+    res = {"worst_channel_rel_l2": float(f"{ratio.max():.3e}")}
+    centre = [(f, a) for f, a, _ in w.tones if abs(f * w.P - round(f * w.P)) < 1e-9]
+    if centre:
+        f, a = min(centre, key=lambda t: t[1])
+        k = int(round(f * w.P)) % w.P
+        if k < ratio.size:
+            res["weakest_tone"] = {"channel": k, "amplitude": a, "rel_l2": float(f"{ratio[k]:.3e}")}
+    return res
+
+
 def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
     """Throughput and error of each precision form on workload w."""
     from paper_2408_16551_amd.pfb import Plan
@@ -122,6 +142,7 @@ def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
             "dft_useful_tflops": round(flops / (dft_ms * 1e-3) / 1e12, 2),
             "dft_mfma_frac": round(flops * MFMA_FLOP_MULT[form] / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS[form], 4),
         }
+        res[entry].update(channel_errors(got, ref, w, fr))
         # FIR stage bytes: FP32 input once, output FP32 (or 1 + 1/32 bytes per
         # float in the block-scaled form, which the FIR writes directly).
         fir_out_b = (1.0 + 1.0 / 32) if form == "mxfp8" else 4.0
@@ -163,6 +184,74 @@ def cpu_baseline(w, target_s=12.0):
     return {"value": round(n * w.P / dt / 1e9, 6), "unit": "GSamples/s", "cores": o.threads(), "kind": "oracle",
             "sample": f"first {n} of {F} frames ({n * w.P} input samples) of {w.name}, FP64 direct FIR + "
                       f"direct-sum DFT, {dt:.1f} s wall on {o.threads()} OpenMP threads"}
+
+
+def numpy_pfb(x, P, M, h, dtype):
+    """The filter bank written directly in NumPy, the kind of CPU baseline the
+    paper compares against: the polyphase FIR of Eq. (20) as M shifted
+    multiply-adds over the frames (tap m of branch p is h[(M-1-m)P + p]), then
+    numpy.fft across the branches of each frame."""
+    F = x.size // P
+    X = x[: F * P].reshape(F, P).astype(dtype)
+    hb = np.asarray(h).reshape(M, P).astype(np.finfo(dtype).dtype)  # real taps
+    y = hb[M - 1] * X
+    for m in range(1, min(M, F)):
+        y[m:] += hb[M - 1 - m] * X[: F - m]
+    return np.fft.fft(y, axis=1) if np.iscomplexobj(y) else np.fft.rfft(y, axis=1)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_context(w, target_s=4.0):
+    """Beside the oracle on every host core: the oracle on one core, and the
+    NumPy filter bank in FP32 and FP64 (one process; NumPy's loops and FFT
+    run on one core), each on a bounded sample of frames."""
+    from oracle import Oracle
+    o = Oracle()
+    h = o.window(w.P, w.M, w.window)
+    F = w.x.size // w.P
+    all_threads = o.threads()
+    res = {"cpu_model": cpu_model(), "host_threads": all_threads}
+    o.set_threads(1)
+    try:
+        n, dt = 8, 0.0
+        while n < F:
+            t = time.perf_counter()
+            o.pfb(w.x, w.P, w.M, h, frames=np.arange(n, dtype=np.int64))
+            dt = time.perf_counter() - t
+            if dt >= target_s / 10:
+                break
+            n *= 2
+        n = int(min(F, max(n, n * target_s / max(dt, 1e-9))))
+        t = time.perf_counter()
+        o.pfb(w.x, w.P, w.M, h, frames=np.arange(n, dtype=np.int64))
+        dt = time.perf_counter() - t
+        res["oracle_one_core"] = {"value": round(n * w.P / dt / 1e9, 6), "unit": "GSamples/s",
+                                  "sample": f"first {n} of {F} frames, {dt:.1f} s"}
+    finally:
+        o.set_threads(all_threads)
+    nf = min(F, 8192)
+    xs = w.x[: nf * w.P]
+    check = o.pfb(xs, w.P, w.M, h, frames=np.arange(min(nf, w.M + 2), dtype=np.int64))
+    for name, dt_ in (("fp32", np.complex64 if w.complex_input else np.float32),
+                      ("fp64", np.complex128 if w.complex_input else np.float64)):
+        dt_ = np.dtype(dt_)
+        numpy_pfb(xs[: 64 * w.P], w.P, w.M, h, dt_)  # warm up the FFT plan
+        t = time.perf_counter()
+        X = numpy_pfb(xs, w.P, w.M, h, dt_)
+        sec = time.perf_counter() - t
+        res[f"numpy_{name}"] = {"value": round(nf * w.P / sec / 1e9, 6), "unit": "GSamples/s", "cores": 1,
+                                "rel_l2_vs_oracle_first_frames": float(f"{rel_l2(X[: check.shape[0]], check):.2e}"),
+                                "sample": f"first {nf} of {F} frames, {sec:.2f} s"}
+    return res
 
 
 def ops_bench(torch, steps=10):
@@ -465,6 +554,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w)
+        result["cpu_context"] = cpu_context(w)
     print(json.dumps(result), flush=True)
 
 

@@ -57,6 +57,8 @@ def _load(path: str | None = None):
     lib = ctypes.CDLL(p)
     d, i64, i, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
     lib.oracle_threads.restype = i
+    lib.oracle_set_threads.argtypes = [i]
+    lib.oracle_set_threads.restype = None
     lib.oracle_twiddle.argtypes = [i64, i64, ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.oracle_twiddle.restype = None
     lib.oracle_window.argtypes = [i64, i64, i, vp]
@@ -97,6 +99,10 @@ class Oracle:
 
     def threads(self) -> int:
         return int(self.lib.oracle_threads())
+
+    def set_threads(self, n: int) -> None:
+        """OpenMP threads of the calls that follow (timing only)."""
+        self.lib.oracle_set_threads(int(n))
 
     def twiddle(self, r: int, P: int) -> complex:
         """cos(2 pi r/P) + i sin(2 pi r/P)."""

@@ -60,6 +60,15 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Thread count of the OpenMP loops that follow (n >= 1); for timing only. */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * cos(2*pi*r/P) and sin(2*pi*r/P) for an integer r, with r reduced modulo P
  * in integer arithmetic first.  The angle is split into a whole number of
