@@ -549,7 +549,8 @@ def main():
         log("[bench] serving workload")
         result["serving"] = [serving_bench(torch, prec, bud) for prec in ("fp8", "bf16x3")
                              for bud in (8 << 30, 256 << 20)]
-        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True) for prec in ("fp8", "bf16x3")]
+        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho) for rho in (0.5, 0.8)
+                              for prec in ("fp8", "bf16x3")]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
