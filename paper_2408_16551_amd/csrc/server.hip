@@ -224,19 +224,28 @@ void tina_server_s::loop() {
         }
 
         // Build the step: every active request whose input is on the device.
+        // The workspace and the step graph's grid hold max_active requests of
+        // frames_per_step frames each; when fewer are ready, each may take
+        // proportionally more, so a lone long request does not crawl through
+        // many small steps.
         items.clear();
         in_step.clear();
         std::vector<Req*> empty_done;
         {
             std::unique_lock<std::mutex> lk(mu);
+            int64_t n_ready = 0;
             for (Req* q : active) {
                 if (!q->in_ready) q->in_ready = hipEventQuery(q->ev_in) == hipSuccess;
+                if (q->in_ready && q->r.n_samples > 0) ++n_ready;
+            }
+            const int64_t quota = cfg.frames_per_step * std::max<int64_t>(1, cfg.max_active / std::max<int64_t>(1, n_ready));
+            for (Req* q : active) {
                 if (!q->in_ready) continue;
                 if (q->r.n_samples == 0) { empty_done.push_back(q); continue; }
                 LStream& ls = streams[q->r.stream_id];
                 const int64_t P = ls.plan->P;
                 const int64_t r = ls.state->residue;
-                const int64_t s = std::min(q->r.n_samples - q->samples_done, cfg.frames_per_step * P - r);
+                const int64_t s = std::min(q->r.n_samples - q->samples_done, quota * P - r);
                 tina_pfb_work w{};
                 w.plan = ls.plan;
                 w.state = ls.state;
