@@ -12,7 +12,9 @@
  * and are admitted while a slot is free and their device buffers (input and
  * output) fit the HBM budget; a stream runs one request at a time, in order.
  * Each step gives every admitted request whose input has reached the device
- * up to `frames_per_step` frames of work and runs them together as one
+ * up to `frames_per_step` frames of work (times max_active / ready requests,
+ * rounded down, when fewer than max_active are ready: the step workspace is
+ * shared) and runs them together as one
  * batched launch per stage (tina_pfb_batch.h), optionally replayed from a
  * captured HIP graph, so requests that arrive while others run join at the
  * next step and their work overlaps on the device.  Input copies to the
@@ -43,7 +45,7 @@ typedef struct tina_server_config {
     int32_t max_active;        /* requests admitted at once (slots), >= 1 */
     int32_t max_queued;        /* requests waiting for admission; submit returns BUSY beyond */
     int64_t hbm_budget_bytes;  /* device arena for request input and output buffers */
-    int64_t frames_per_step;   /* frames of work per request per step, >= 1 */
+    int64_t frames_per_step;   /* frames of work per request per step with every slot busy, >= 1 */
     int32_t use_graph;         /* nonzero: each step replays a captured HIP graph */
     int32_t max_channels;      /* largest P any stream will use (sizes the step workspace) */
 } tina_server_config;
