@@ -220,7 +220,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         fa.nparts = p->W >= 32 ? p->W / 32 : 1;  // VEC = 1 in the batched FIR: one part per 32 lanes
         // Operand-form FIR output inside the item's F * W floats: E4M3 codes
         // then scales, or the bf16 piece(s) one after the other.
-        fa.qmode = form_fir_qmode(b->form);
+        fa.qmode = batch_fir_qmode(b->form);
         if (fa.qmode != 0) {
             fa.y = nullptr;
             fa.q = (uint8_t*)(b->ws + ws_off);
@@ -313,9 +313,9 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), form_fir_qmode(b->form), grid_fir, s));
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), batch_fir_qmode(b->form), grid_fir, s));
     if (always || b->h_table->gemm_units > 0)
-        HIP_TRY(launch_gemm_batch(b->d_table, b->form, form_fir_qmode(b->form) != 0, tune.gemm_tile_n, (int)grid_gemm, s));
+        HIP_TRY(launch_gemm_batch(b->d_table, b->form, batch_fir_qmode(b->form) != 0, tune.gemm_tile_n, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }

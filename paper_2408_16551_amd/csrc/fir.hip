@@ -37,14 +37,15 @@ int pick_vec(const FirArgs& a) {
     // Block-scaled output: 4 floats per thread up to 16 taps (the per-block
     // maximum is then shared among 8 lanes, and a lane's 4 codes leave in one
     // store; measured faster than 1 or 2 at 16 taps).
-    if (a.qmode == QM_MX && a.M <= 16) vec = 4;
+    if ((a.qmode == QM_MX || a.qmode == QM_FP8F) && a.M <= 16) vec = 4;
     const FirTune tune = fir_tune();
     if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec;
     if (vec == 4 && a.M > 16) vec = 2;  // widest ring per vector width: 16 taps (VEC 4), 32 (VEC 2), 64 (VEC 1)
     if (vec == 2 && a.M > 32) vec = 1;
     auto out_ok = [&](int v) {
-        if (a.qmode == QM_MX) return aligned(a.q, 4) && a.ldq % 4 == 0;  // codes leave in 4-byte stores
-        if (a.qmode != QM_NONE)  // bf16: 2 v bytes per store
+        if (a.qmode == QM_AMAXONLY) return true;  // nothing but the partial maxima
+        if (a.qmode == QM_MX || a.qmode == QM_FP8F) return aligned(a.q, 4) && a.ldq % 4 == 0;  // 4-byte code stores
+        if (a.qmode != QM_NONE)  // bf16 / fp16: 2 v bytes per store
             return aligned(a.q, 2 * v) && (a.q1 == nullptr || aligned(a.q1, 2 * v)) && a.ldq % v == 0;
         return aligned(a.y, 4 * v) && a.ldy % v == 0;
     };
@@ -79,6 +80,16 @@ __global__ void gather_batch_kernel(const BatchTable* __restrict__ t) {
     }
 }
 
+// e_f = frame_exponent(largest partial maximum of frame f, limit).
+__global__ void frame_exponent_kernel(const float* __restrict__ amax, int nparts, int64_t F, float limit,
+                                      int32_t* __restrict__ fexp) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    float m = 0.0f;
+    for (int q = 0; q < nparts; ++q) m = fmaxf(m, amax[f * nparts + q]);
+    fexp[f] = frame_exponent(m, limit);
+}
+
 }  // namespace
 
 hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s) {
@@ -99,6 +110,36 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
         const int ct = a.W / vec;
         const int gw = ct < 32 ? ct : 32;
         a.nparts = ct / gw;
+    }
+    if (qmode_frame_scaled(a.qmode)) {
+        // Per-frame scaled codes: the frame's maximum must be known before its
+        // first code is written, and a frame spans many blocks.  Pass 1 finds
+        // the partial maxima, a small kernel the exponents, and pass 2
+        // recomputes the FIR (reading the input again is cheaper than writing
+        // and reading FP32 rows) and writes the scaled codes.
+        if (!a.amax || !a.fexp || !a.q || (a.qmode == QM_FP16FX2 && !a.q1)) return hipErrorInvalidValue;
+        FirArgs p1 = a;
+        p1.qmode = QM_AMAXONLY;
+        p1.y = nullptr;
+        p1.q = p1.q1 = p1.qs = nullptr;
+        const int v1 = pick_vec(p1);
+        {
+            const int ct = a.W / v1;
+            p1.nparts = ct / (ct < 32 ? ct : 32);
+        }
+        hipError_t e = launch_fir_mode_amaxonly(p1, v1, s);
+        if (e != hipSuccess) return e;
+        const float limit = a.qmode == QM_FP8F ? 448.0f : 32768.0f;
+        hipLaunchKernelGGL(frame_exponent_kernel, dim3((unsigned)((a.F + 255) / 256)), dim3(256), 0, s, p1.amax,
+                           p1.nparts, a.F, limit, a.fexp);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        a.nparts = p1.nparts;
+        switch (a.qmode) {
+            case QM_FP8F: return launch_fir_mode_fp8f(a, vec, s);
+            case QM_FP16F: return launch_fir_mode_fp16f(a, vec, s);
+            default: return launch_fir_mode_fp16fx2(a, vec, s);
+        }
     }
     if (a.qmode == QM_MX) return launch_fir_mode_mx(a, vec, s);
     if (a.qmode == QM_BF16) return launch_fir_mode_bf16(a, vec, s);

@@ -12,11 +12,32 @@
 namespace tina {
 
 // Output modes of the FIR: FP32 rows, FP32 rows plus per-frame partial
-// maxima (per-frame scaled forms), block-scaled FP8 codes and scales.
-enum FirOut : int { FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4 };
+// maxima (per-frame scaled forms), block-scaled FP8 codes and scales, bf16
+// pieces, partial maxima alone, per-frame scaled FP8 or fp16 pieces.
+enum FirOut : int {
+    FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4,
+    FIR_OUT_AMAXONLY = 5, FIR_OUT_FP8F = 6, FIR_OUT_FP16F = 7, FIR_OUT_FP16FX2 = 8
+};
 // Operand-form output of the FIR (FirArgs::qmode): none (FP32 y), block-scaled
-// FP8 codes and scales, bf16 (RNE), or bf16 hi + lo (lo = RNE(y - hi)).
-enum QMode : int { QM_NONE = 0, QM_MX = 1, QM_BF16 = 2, QM_BF16X2 = 3 };
+// FP8 codes and scales, bf16 (RNE), bf16 hi + lo (lo = RNE(y - hi)); with
+// the frame's scale 2^-fexp[f] applied: FP8 E4M3 (saturated at 448), fp16,
+// fp16 hi + lo (lo = RNE((x - hi) 2^11)); or only the partial maxima.
+enum QMode : int {
+    QM_NONE = 0, QM_MX = 1, QM_BF16 = 2, QM_BF16X2 = 3, QM_FP8F = 4, QM_FP16F = 5, QM_FP16FX2 = 6, QM_AMAXONLY = 7
+};
+constexpr int mode_qm(int mode) {
+    return mode == FIR_OUT_MX ? QM_MX
+         : mode == FIR_OUT_BF16 ? QM_BF16
+         : mode == FIR_OUT_BF16X2 ? QM_BF16X2
+         : mode == FIR_OUT_FP8F ? QM_FP8F
+         : mode == FIR_OUT_FP16F ? QM_FP16F
+         : mode == FIR_OUT_FP16FX2 ? QM_FP16FX2
+         : mode == FIR_OUT_AMAXONLY ? QM_AMAXONLY : QM_NONE;
+}
+// Bytes per operand element and whether a second piece is written.
+constexpr int qm_bytes(int qm) { return (qm == QM_MX || qm == QM_FP8F) ? 1 : 2; }
+constexpr bool qm_two_pieces(int qm) { return qm == QM_BF16X2 || qm == QM_FP16FX2; }
+constexpr bool qm_stores(int qm) { return qm != QM_NONE && qm != QM_AMAXONLY; }
 
 // Launch-shape override for tuning sweeps: TINA_FIR_TUNE="vec,tf,nt"
 // (vec 0 and tf 0 keep the defaults, vec 1/2/4 forces the vector width where
@@ -33,6 +54,10 @@ hipError_t launch_fir_mode_amax(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_mx(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_bf16(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_bf16x2(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_amaxonly(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_fp8f(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_fp16f(FirArgs& a, int vec, hipStream_t s);
+hipError_t launch_fir_mode_fp16fx2(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_batch_mode_f32(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_amax(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_mx(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
@@ -290,6 +315,44 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
             if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
         }
         if ((col & (GL - 1)) == 0) out.s8(u, (uint8_t)(e + 127));
+    } else if constexpr (QM == QM_FP8F) {
+        // The frame's scale, then the same packing as the block-scaled codes.
+        const float sc = ldexpf(1.0f, -a.fexp[f]);
+        float x[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) x[v] = fminf(fmaxf(vget<VEC>(acc, v) * sc, -448.0f), 448.0f);
+        if constexpr (VEC == 4) {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
+            out.q(0, u, (uint32_t)w);
+        } else if constexpr (VEC == 2) {
+            const uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false) & 0xffffu;
+            const uint32_t w1 = dpp_read<0xF5>(w);
+            if ((col & 1) == 0) out.q(0, u, w | (w1 << 16));
+        } else {
+            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false) & 0xffu;
+            const uint32_t c1 = dpp_read<0x55>(c), c2 = dpp_read<0xAA>(c), c3 = dpp_read<0xFF>(c);
+            if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
+        }
+    } else if constexpr (QM == QM_FP16F || QM == QM_FP16FX2) {
+        const float sc = ldexpf(1.0f, -a.fexp[f]);
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const float x = vget<VEC>(acc, v) * sc;
+            const _Float16 h = (_Float16)x;
+            hi[v] = __builtin_bit_cast(uint16_t, h);
+            lo[v] = __builtin_bit_cast(uint16_t, (_Float16)((x - (float)h) * 2048.0f));
+        }
+        auto put = [&](int piece, const uint32_t (&h)[4]) {
+            if constexpr (VEC == 4) out.q(piece, u, (uint64_t)(h[0] | (h[1] << 16)) | ((uint64_t)(h[2] | (h[3] << 16)) << 32));
+            else if constexpr (VEC == 2) out.q(piece, u, h[0] | (h[1] << 16));
+            else out.q(piece, u, (uint16_t)h[0]);
+        };
+        put(0, hi);
+        if constexpr (QM == QM_FP16FX2) put(1, lo);
+    } else if constexpr (QM == QM_AMAXONLY) {
+        fir_amax<VEC, true>(a, acc, f, col, gw);
     } else if constexpr (QM == QM_BF16 || QM == QM_BF16X2) {
         uint32_t hi[4], lo[4];
 #pragma unroll
@@ -364,12 +427,12 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
     // take the same path.
     constexpr int SB = (VEC == 4 ? 8 : 16) < MT ? (VEC == 4 ? 8 : 16) : MT;
     const int64_t nsc = a.W / 32;
-    constexpr int QB = QM == QM_MX ? 1 : 2;  // bytes per operand element
+    constexpr int QB = qm_bytes(QM);  // bytes per operand element
     auto sink_ptr = [&](int64_t fb) {
         PtrSink<VEC, NT> o;
         o.yb = QM ? nullptr : a.y + fb * a.ldy + j0;
-        o.qb[0] = QM ? a.q + (fb * a.ldq + j0) * QB : nullptr;
-        o.qb[1] = QM == QM_BF16X2 ? a.q1 + (fb * a.ldq + j0) * QB : nullptr;
+        o.qb[0] = qm_stores(QM) ? a.q + (fb * a.ldq + j0) * QB : nullptr;
+        o.qb[1] = qm_two_pieces(QM) ? a.q1 + (fb * a.ldq + j0) * QB : nullptr;
         o.sb = QM == QM_MX ? a.qs + fb * nsc + j0 / 32 : nullptr;
         o.ldy = a.ldy;
         o.ldq = a.ldq * QB;
@@ -389,9 +452,11 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
             const uint32_t vin = (uint32_t)j0 * 4u;
             const int32_t w4 = a.W * 4;
             BufSink<VEC, NT> o;
-            if constexpr (QM != QM_NONE) {
+            if constexpr (QM == QM_AMAXONLY) {
+                // partial maxima only: nothing is stored through the sink
+            } else if constexpr (QM != QM_NONE) {
                 o.rq[0] = make_rsrc(a.q + fu * a.ldq * QB, (a.F - fu) * a.ldq * QB);
-                if constexpr (QM == QM_BF16X2) o.rq[1] = make_rsrc(a.q1 + fu * a.ldq * QB, (a.F - fu) * a.ldq * QB);
+                if constexpr (qm_two_pieces(QM)) o.rq[1] = make_rsrc(a.q1 + fu * a.ldq * QB, (a.F - fu) * a.ldq * QB);
                 if constexpr (QM == QM_MX) o.rs = make_rsrc(a.qs + fu * nsc, (a.F - fu) * nsc);
                 o.vq = (uint32_t)(j0 * QB);
                 o.vs = (uint32_t)(j0 / 32);
@@ -447,7 +512,7 @@ __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __rest
 template <int VEC, int MT, bool EXACT, int MODE>
 hipError_t launch_one(FirArgs& a, hipStream_t s) {
     constexpr bool AMAX = MODE == FIR_OUT_AMAX;
-    constexpr int QM = MODE == FIR_OUT_MX ? QM_MX : (MODE == FIR_OUT_BF16 ? QM_BF16 : (MODE == FIR_OUT_BF16X2 ? QM_BF16X2 : QM_NONE));
+    constexpr int QM = mode_qm(MODE);
     const int ct = a.W / VEC;
     // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
     // least 16) keeps the halo re-reads in L2 while leaving enough waves to
@@ -504,7 +569,7 @@ hipError_t launch_mode(FirArgs& a, int vec, hipStream_t s) {
 template <int MODE>
 hipError_t launch_batch_mode(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
     constexpr bool AMAX = MODE == FIR_OUT_AMAX;
-    constexpr int QM = MODE == FIR_OUT_MX ? QM_MX : (MODE == FIR_OUT_BF16 ? QM_BF16 : (MODE == FIR_OUT_BF16X2 ? QM_BF16X2 : QM_NONE));
+    constexpr int QM = mode_qm(MODE);
     auto go = [&](auto mt_tag) -> hipError_t {
         constexpr int MT = decltype(mt_tag)::value;
         if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, AMAX, QM>), dim3(grid), dim3(256), 0, s, t);

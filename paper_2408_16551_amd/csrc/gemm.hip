@@ -50,16 +50,6 @@ constexpr int RS = ROWB + 16;         // LDS row stride: 16-byte pad keeps 16-by
 constexpr int NT = 256;               // threads per block
 constexpr int GROUP_M = 16;           // m-tiles swept per column of n-tiles
 
-// Per-frame scale 2^e with the frame's largest |y| * 2^-e <= limit.
-__device__ inline int frame_exponent(float amax, float limit) {
-    if (!(amax > 0.0f) || !isfinite(amax)) return 0;
-    int e;
-    frexpf(amax / limit, &e);  // amax/limit in [2^(e-1), 2^e)
-    while (e > -120 && ldexpf(limit, e - 1) >= amax) --e;
-    while (e < 120 && ldexpf(limit, e) < amax) ++e;
-    return e;
-}
-
 __device__ inline uint32_t bf16_pair(float a, float b) {
     return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)b) << 16);
 }
@@ -534,8 +524,10 @@ __device__ __forceinline__ void gemm_tile_fused(const FusedArgs& fa, int64_t m0,
 
 // Raw-operand tile: A arrives in the operand form (NP pieces of EB-byte
 // elements, K contiguous, row stride g.lda elements; block-scaled FP8 also
-// with a scale byte per 32 K), so a K tile of A is copied to LDS like B, with
-// no conversion and a quarter (FP8) or half (bf16) of the FP32 A registers.
+// with a scale byte per 32 K; per-frame scaled forms with the frame's
+// exponent in g.fexp, undone in the epilogue), so a K tile of A is copied to
+// LDS like B, with no conversion and a quarter (FP8) or half (16-bit) of the
+// FP32 A registers.
 // One-piece forms keep two LDS buffers, so one barrier per K tile suffices
 // and the stores of tile t + 1 overlap other waves' products on tile t;
 // two-piece forms keep one buffer (two barriers).
@@ -544,6 +536,7 @@ struct RawSmem {
     static constexpr int NP = FT<FORM>::NP, BN = 64 * WN, LB = NP == 1 ? 2 : 1;
     uint8_t tiles[LB][NP * (BM + BN) * RS];
     uint32_t mxs[LB][FT<FORM>::MX ? BM + BN : 1];  // scale words of the K tile: A rows, then B rows
+    float fsc[FT<FORM>::SCALED ? BM : 1];           // per-frame scaled forms: 2^e_f of the tile's rows
 };
 
 template <int FORM, int WN>
@@ -556,7 +549,6 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
     constexpr int BCH = BN * (ROWB / 16) / NT;  // B 16-byte chunks per thread per piece
     constexpr int NSLAB = ROWB / SLAB;
     constexpr int RD = SLAB / 32;
-    static_assert(!ft::SCALED, "per-frame scaled forms convert A in the tile");
     static_assert(!ft::MX || (BM + BN == NT && NP == 1), "block-scaled form: one scale word per thread");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -621,14 +613,16 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
         if constexpr (ft::MX) sm.mxs[buf][tid] = r.sc;
     };
 
-    static_assert(FORM != FORM_FP16X3, "the second accumulator is not kept here");
-    f32x16 acc[2][WN], acc2[2][WN];  // acc2 is never read or written by these forms
+    f32x16 acc[2][WN], acc2[2][WN];  // acc2: the fp16 cross terms (FP16X3 only)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+            for (int v = 0; v < 16; ++v) {
+                acc[i][j][v] = 0.f;
+                if constexpr (FORM == FORM_FP16X3) acc2[i][j][v] = 0.f;
+            }
 
     auto compute = [&](int buf) {
         const uint8_t* As = sm.tiles[buf];
@@ -669,6 +663,9 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
     };
 
     __syncthreads();  // the previous tile of a persistent block is done with LDS
+    if constexpr (ft::SCALED) {  // read by the epilogue, after the barriers below
+        if (tid < BM) sm.fsc[tid] = m0 + tid < g.F ? ldexpf(1.0f, g.fexp[m0 + tid]) : 1.0f;
+    }
     const int nk = (g.K + BK - 1) / BK;
     Stage r;
     load(r, 0);
@@ -687,7 +684,7 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
         }
         __syncthreads();
     }
-    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, nullptr);
+    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, ft::SCALED ? sm.fsc : nullptr);
 }
 
 template <int FORM, int WN>
@@ -764,7 +761,7 @@ hipError_t launch_raw(const GemmArgs& g, hipStream_t s) {
 
 }  // namespace
 
-bool gemm_raw_form(int form) { return form == FORM_MXFP8 || form == FORM_BF16 || form == FORM_BF16X3; }
+bool gemm_raw_form(int form) { return form != FORM_FP32; }
 
 hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s) {
     const dim3 gd(grid), bd(NT);
@@ -828,6 +825,9 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
             case FORM_BF16: return launch_raw<FORM_BF16>(g, s);
             case FORM_BF16X3: return g.Aq1 ? launch_raw<FORM_BF16X3>(g, s) : hipErrorInvalidValue;
             case FORM_MXFP8: return (g.K % 128 == 0 && g.Aqs) ? launch_raw<FORM_MXFP8>(g, s) : hipErrorInvalidValue;
+            case FORM_FP8: return g.fexp ? launch_raw<FORM_FP8>(g, s) : hipErrorInvalidValue;
+            case FORM_FP16: return g.fexp ? launch_raw<FORM_FP16>(g, s) : hipErrorInvalidValue;
+            case FORM_FP16X3: return (g.fexp && g.Aq1) ? launch_raw<FORM_FP16X3>(g, s) : hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }

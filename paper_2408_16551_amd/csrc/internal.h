@@ -68,6 +68,11 @@ struct FirArgs {
     int64_t ldq;
     uint8_t* qs;
     int32_t qmode;
+    // Per-frame scaled operand output (qmode 4 FP8 E4M3, 5 fp16, 6 fp16 hi +
+    // lo): launch_fir first finds every frame's maximum (into amax), then its
+    // exponent e_f (fexp[f], the frame's values are scaled by 2^-e_f), then
+    // writes the scaled codes.
+    int32_t* fexp;
 };
 // Chooses the vector width and unroll; returns the number of partial maxima
 // per frame through a.nparts when a.amax is set.
@@ -99,6 +104,7 @@ struct GemmArgs {
     const uint8_t* Aq;
     const uint8_t* Aq1;
     const uint8_t* Aqs;
+    const int32_t* fexp;   // per-frame scaled forms with A in operand form: A row f carries 2^-fexp[f]
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
 // The FIR fused into the FP32 GEMM (g.A unused; x describes the input stream
@@ -172,9 +178,34 @@ constexpr int kGemmBM = 128, kGemmBN = 128;
 
 hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
                              hipStream_t s);
-// FirArgs::qmode the FIR writes for a DFT form (0: FP32 y).
+// FirArgs::qmode the FIR writes for a DFT form on the single-stream path (0:
+// FP32 y): every form but FP32 takes its operand straight from the FIR.
 inline int form_fir_qmode(int form) {
-    return form == FORM_MXFP8 ? 1 : (form == FORM_BF16 ? 2 : (form == FORM_BF16X3 ? 3 : 0));
+    switch (form) {
+        case FORM_MXFP8: return 1;
+        case FORM_BF16: return 2;
+        case FORM_BF16X3: return 3;
+        case FORM_FP8: return 4;
+        case FORM_FP16: return 5;
+        case FORM_FP16X3: return 6;
+        default: return 0;
+    }
+}
+// The batched path keeps the per-frame scaled forms on FP32 y plus partial
+// maxima, converted in the GEMM tile.
+inline int batch_fir_qmode(int form) { return form_scaled(form) ? 0 : form_fir_qmode(form); }
+// qmode values whose codes carry a per-frame scale.
+inline bool qmode_frame_scaled(int qm) { return qm >= 4 && qm <= 6; }
+
+// Per-frame scale 2^e with the frame's largest |y| * 2^-e <= limit (448 for
+// FP8 E4M3, 32768 for fp16); 0 for a zero or non-finite maximum.
+__device__ inline int frame_exponent(float amax, float limit) {
+    if (!(amax > 0.0f) || !isfinite(amax)) return 0;
+    int e;
+    frexpf(amax / limit, &e);  // amax/limit in [2^(e-1), 2^e)
+    while (e > -120 && ldexpf(limit, e - 1) >= amax) --e;
+    while (e < 120 && ldexpf(limit, e) < amax) ++e;
+    return e;
 }
 // tile_n: the table's GEMM tile columns (kGemmBN for every form; 2 * kGemmBN
 // also for FP32 with A in FP32).

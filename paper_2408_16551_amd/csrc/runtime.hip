@@ -157,7 +157,8 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
             return bail(TINA_ERR_OUT_OF_MEMORY, "plan: workspace allocation");
         if (p->ch_frames > 0 && form_scaled(form)) {
             p->amax_parts_cap = p->W / 32 > 1 ? p->W / 32 : 1;  // the most parts: one per 32 lanes at VEC = 1
-            if (hipMalloc(&p->amax, p->ch_frames * p->amax_parts_cap * sizeof(float)) != hipSuccess)
+            if (hipMalloc(&p->amax, p->ch_frames * p->amax_parts_cap * sizeof(float)) != hipSuccess ||
+                hipMalloc(&p->fexp, p->ch_frames * sizeof(int32_t)) != hipSuccess)
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: scale workspace allocation");
         }
     }
@@ -265,14 +266,18 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.F = Fc;
             fa.amax = form_scaled(form) ? p->amax : nullptr;
             // Operand-form FIR output in the FP32 workspace (4 bytes per float):
-            // E4M3 codes then scales, or the bf16 piece(s) one after the other.
+            // E4M3 codes (then the block scales), or the 16-bit piece(s) one
+            // after the other; per-frame scaled forms also keep the frames'
+            // exponents beside their partial maxima.
             fa.qmode = form_fir_qmode(form);
             if (fa.qmode != 0) {
                 fa.y = nullptr;
                 fa.q = (uint8_t*)p->ws;
                 fa.ldq = p->W;
                 if (form_mx(form)) fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
-                if (form == TINA_PREC_BF16X3) fa.q1 = (uint8_t*)p->ws + (int64_t)p->ch_frames * p->W * 2;
+                if (form == TINA_PREC_BF16X3 || form == TINA_PREC_FP16X3)
+                    fa.q1 = (uint8_t*)p->ws + (int64_t)p->ch_frames * p->W * 2;
+                if (form_scaled(form)) fa.fexp = p->fexp;
             }
             if (p->dft_algorithm == TINA_DFT_FUSED && fused_supported(fa, form)) {
                 GemmArgs ga{};
@@ -321,6 +326,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             ga.Aq = fa.q;
             ga.Aq1 = fa.q1;
             ga.Aqs = fa.qs;
+            ga.fexp = fa.fexp;
             HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
     }

@@ -53,6 +53,7 @@ struct tina_pfb_plan_s {
     int cus = 256;
     float* ws = nullptr;
     float* amax = nullptr;
+    int32_t* fexp = nullptr;    // per-frame scale exponents of a workspace piece (per-frame scaled forms)
     int64_t ch_frames = 0;
     int64_t amax_parts_cap = 0;
     // Stage timing (tina_pfb_profile_*): recorded event pairs per stage.
@@ -79,11 +80,11 @@ struct tina_pfb_plan_s {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         clear_events();
-        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax, (void*)fft_mat1, (void*)fft_mat3,
-                        (void*)fft_tw, (void*)g32, (void*)hist[0], (void*)hist[1]})
+        for (void* p : {(void*)h64, (void*)h32, B[0], B[1], (void*)ws, (void*)amax, (void*)fexp, (void*)fft_mat1,
+                        (void*)fft_mat3, (void*)fft_tw, (void*)g32, (void*)hist[0], (void*)hist[1]})
             if (p) (void)hipFree(p);
         g32 = hist[0] = hist[1] = nullptr;
-        h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr;
+        h64 = nullptr; h32 = nullptr; B[0] = B[1] = nullptr; ws = nullptr; amax = nullptr; fexp = nullptr;
         fft_mat1 = fft_mat3 = fft_tw = nullptr;
     }
 };
