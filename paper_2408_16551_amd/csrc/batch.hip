@@ -82,6 +82,7 @@ struct tina_pfb_batch_s {
     int64_t ws_floats = 0;
     float* amax = nullptr;       // per-frame partial maxima (scaled forms)
     int64_t amax_floats = 0;
+    int32_t* fexp = nullptr;     // per-frame scale exponents (scaled forms), amax_floats entries
     BatchTable* d_table = nullptr;
     BatchTable* h_table = nullptr;  // pinned
     size_t table_bytes = 0;
@@ -99,9 +100,9 @@ struct tina_pfb_batch_s {
         graphs.clear();
         if (table_free) (void)hipEventDestroy(table_free);
         if (h_table) (void)hipHostFree(h_table);
-        for (void* p : {(void*)ws, (void*)amax, (void*)d_table})
+        for (void* p : {(void*)ws, (void*)amax, (void*)fexp, (void*)d_table})
             if (p) (void)hipFree(p);
-        table_free = nullptr; h_table = nullptr; ws = nullptr; amax = nullptr; d_table = nullptr;
+        table_free = nullptr; h_table = nullptr; ws = nullptr; amax = nullptr; fexp = nullptr; d_table = nullptr;
     }
 };
 
@@ -219,14 +220,17 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         fa.amax = form_scaled(b->form) ? b->amax + amax_off : nullptr;
         fa.nparts = p->W >= 32 ? p->W / 32 : 1;  // VEC = 1 in the batched FIR: one part per 32 lanes
         // Operand-form FIR output inside the item's F * W floats: E4M3 codes
-        // then scales, or the bf16 piece(s) one after the other.
-        fa.qmode = batch_fir_qmode(b->form);
+        // (then the block scales), or the 16-bit piece(s) one after the other;
+        // per-frame scaled forms keep one exponent per frame (amax_off counts
+        // at least one part per frame, so it also places them).
+        fa.qmode = form_fir_qmode(b->form);
         if (fa.qmode != 0) {
             fa.y = nullptr;
             fa.q = (uint8_t*)(b->ws + ws_off);
             fa.ldq = p->W;
             if (form_mx(b->form)) fa.qs = fa.q + mx_codes_bytes(F, p->W);
-            if (b->form == TINA_PREC_BF16X3) fa.q1 = fa.q + F * p->W * 2;
+            if (b->form == TINA_PREC_BF16X3 || b->form == TINA_PREC_FP16X3) fa.q1 = fa.q + F * p->W * 2;
+            if (form_scaled(b->form)) fa.fexp = b->fexp + amax_off;
         }
         ws_off += F * p->W;
         amax_off += F * fa.nparts;
@@ -247,6 +251,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.Aq = fa.q;
         ga.Aq1 = fa.q1;
         ga.Aqs = fa.qs;
+        ga.fexp = fa.fexp;
         bi.fir_tf = TF;
         const int64_t runs = (F + TF - 1) / TF;
         fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
@@ -312,10 +317,11 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
                           bool always, int64_t fixed_gemm_grid = 0) {
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
+    const int qmode = form_fir_qmode(b->form);
     if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), batch_fir_qmode(b->form), grid_fir, s));
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), qmode, grid_fir, s));
     if (always || b->h_table->gemm_units > 0)
-        HIP_TRY(launch_gemm_batch(b->d_table, b->form, batch_fir_qmode(b->form) != 0, tune.gemm_tile_n, (int)grid_gemm, s));
+        HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }
@@ -465,7 +471,9 @@ tina_status tina_pfb_batch_create(int device, int precision, int max_items, int6
     if (hipMalloc(&b->ws, b->ws_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: workspace");
     if (form_scaled(precision)) {
         b->amax_floats = b->ws_floats / 16 + 1024;  // F * max(1, W/32) <= F * W / 16 for W >= 16
-        if (hipMalloc(&b->amax, b->amax_floats * 4) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: scale workspace");
+        if (hipMalloc(&b->amax, b->amax_floats * 4) != hipSuccess ||
+            hipMalloc(&b->fexp, b->amax_floats * sizeof(int32_t)) != hipSuccess)
+            return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: scale workspace");
     }
     if (hipMalloc(&b->d_table, b->table_bytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: table");
     if (hipHostMalloc(&b->h_table, b->table_bytes, hipHostMallocDefault) != hipSuccess)

@@ -80,14 +80,39 @@ __global__ void gather_batch_kernel(const BatchTable* __restrict__ t) {
     }
 }
 
-// e_f = frame_exponent(largest partial maximum of frame f, limit).
-__global__ void frame_exponent_kernel(const float* __restrict__ amax, int nparts, int64_t F, float limit,
-                                      int32_t* __restrict__ fexp) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= F) return;
+// Largest value over a wave (all 64 lanes take part).
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// e_f = frame_exponent(largest partial maximum of frame f, limit): one wave
+// per frame, its lanes reading the frame's partial maxima side by side.
+__device__ inline void frame_exponent_wave(const float* __restrict__ amax, int nparts, int64_t f, float limit,
+                                           int32_t* __restrict__ fexp) {
+    const int lane = threadIdx.x & 63;
     float m = 0.0f;
-    for (int q = 0; q < nparts; ++q) m = fmaxf(m, amax[f * nparts + q]);
-    fexp[f] = frame_exponent(m, limit);
+    for (int q = lane; q < nparts; q += 64) m = fmaxf(m, amax[f * nparts + q]);
+    m = wave_max(m);
+    if (lane == 0) fexp[f] = frame_exponent(m, limit);
+}
+
+__global__ __launch_bounds__(256) void frame_exponent_kernel(const float* __restrict__ amax, int nparts, int64_t F,
+                                                             float limit, int32_t* __restrict__ fexp) {
+    const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (f < F) frame_exponent_wave(amax, nparts, f, limit, fexp);  // wave-uniform
+}
+
+// The same for every item of a batch: the grid's waves share each item's
+// frames, item after item.
+__global__ __launch_bounds__(256) void frame_exponent_batch_kernel(const BatchTable* __restrict__ t, float limit) {
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (int it = 0; it < t->n_items; ++it) {
+        const FirArgs& a = t->items[it].fir;
+        for (int64_t f = w; f < a.F; f += nw) frame_exponent_wave(a.amax, a.nparts, f, limit, a.fexp);
+    }
 }
 
 }  // namespace
@@ -130,7 +155,7 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
         hipError_t e = launch_fir_mode_amaxonly(p1, v1, s);
         if (e != hipSuccess) return e;
         const float limit = a.qmode == QM_FP8F ? 448.0f : 32768.0f;
-        hipLaunchKernelGGL(frame_exponent_kernel, dim3((unsigned)((a.F + 255) / 256)), dim3(256), 0, s, p1.amax,
+        hipLaunchKernelGGL(frame_exponent_kernel, dim3((unsigned)((a.F + 3) / 4)), dim3(256), 0, s, p1.amax,
                            p1.nparts, a.F, limit, a.fexp);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -150,6 +175,18 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
 
 hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
                             hipStream_t s) {
+    if (qmode_frame_scaled(qmode)) {  // as in launch_fir: maxima, exponents, codes
+        hipError_t e = launch_fir_batch_mode_amaxonly(t, max_m, all_exact, grid, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(frame_exponent_batch_kernel, dim3(grid), dim3(256), 0, s, t,
+                           qmode == QM_FP8F ? 448.0f : 32768.0f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        switch (qmode) {
+            case QM_FP8F: return launch_fir_batch_mode_fp8f(t, max_m, all_exact, grid, s);
+            case QM_FP16F: return launch_fir_batch_mode_fp16f(t, max_m, all_exact, grid, s);
+            default: return launch_fir_batch_mode_fp16fx2(t, max_m, all_exact, grid, s);
+        }
+    }
     if (qmode == QM_MX) return launch_fir_batch_mode_mx(t, max_m, all_exact, grid, s);
     if (qmode == QM_BF16) return launch_fir_batch_mode_bf16(t, max_m, all_exact, grid, s);
     if (qmode == QM_BF16X2) return launch_fir_batch_mode_bf16x2(t, max_m, all_exact, grid, s);

@@ -63,6 +63,10 @@ hipError_t launch_fir_batch_mode_amax(const BatchTable* t, int max_m, bool all_e
 hipError_t launch_fir_batch_mode_mx(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_bf16(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_bf16x2(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_amaxonly(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_fp8f(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_fp16f(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
+hipError_t launch_fir_batch_mode_fp16fx2(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 
 namespace {
 

@@ -9,4 +9,12 @@ hipError_t launch_fir_mode_fp16f(FirArgs& a, int vec, hipStream_t s) { return la
 
 hipError_t launch_fir_mode_fp16fx2(FirArgs& a, int vec, hipStream_t s) { return launch_mode<FIR_OUT_FP16FX2>(a, vec, s); }
 
+hipError_t launch_fir_batch_mode_fp16f(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
+    return launch_batch_mode<FIR_OUT_FP16F>(t, max_m, all_exact, grid, s);
+}
+
+hipError_t launch_fir_batch_mode_fp16fx2(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
+    return launch_batch_mode<FIR_OUT_FP16FX2>(t, max_m, all_exact, grid, s);
+}
+
 }  // namespace tina

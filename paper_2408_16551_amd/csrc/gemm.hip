@@ -776,6 +776,9 @@ hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n
             case FORM_BF16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16, true>), gd, bd, 0, s, t); break;
             case FORM_BF16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16X3, true>), gd, bd, 0, s, t); break;
             case FORM_MXFP8: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_MXFP8, true>), gd, bd, 0, s, t); break;
+            case FORM_FP8: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP8, true>), gd, bd, 0, s, t); break;
+            case FORM_FP16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16, true>), gd, bd, 0, s, t); break;
+            case FORM_FP16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16X3, true>), gd, bd, 0, s, t); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

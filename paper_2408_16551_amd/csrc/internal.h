@@ -176,10 +176,12 @@ __device__ inline int batch_find(const BatchItem* items, int n, int64_t u, int s
 // GEMM tile geometry shared with the batch planner.
 constexpr int kGemmBM = 128, kGemmBN = 128;
 
+// Per-frame scaled qmodes run three launches: partial maxima, per-frame
+// exponents, scaled codes.
 hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
                              hipStream_t s);
-// FirArgs::qmode the FIR writes for a DFT form on the single-stream path (0:
-// FP32 y): every form but FP32 takes its operand straight from the FIR.
+// FirArgs::qmode the FIR writes for a DFT form (0: FP32 y): every form but
+// FP32 takes its operand straight from the FIR.
 inline int form_fir_qmode(int form) {
     switch (form) {
         case FORM_MXFP8: return 1;
@@ -191,9 +193,6 @@ inline int form_fir_qmode(int form) {
         default: return 0;
     }
 }
-// The batched path keeps the per-frame scaled forms on FP32 y plus partial
-// maxima, converted in the GEMM tile.
-inline int batch_fir_qmode(int form) { return form_scaled(form) ? 0 : form_fir_qmode(form); }
 // qmode values whose codes carry a per-frame scale.
 inline bool qmode_frame_scaled(int qm) { return qm >= 4 && qm <= 6; }
 
