@@ -98,6 +98,10 @@ def sampled_frames(F, M, n, seed):
     return np.array(sorted(fr), dtype=np.int64)
 
 
+FIR_OUT_BYTES = {"fp32": 4.0, "bf16": 2.0, "bf16x3": 4.0, "fp16": 2.0, "fp16x3": 4.0, "fp8": 1.0,
+                 "mxfp8": 1.0 + 1.0 / 32}
+
+
 def channel_errors(got, ref, w, fr):
     """Relative L2 error of each channel over the sampled frames past the
     warm-up: the worst channel, and the channel of the weakest tone placed at
@@ -143,9 +147,10 @@ def forms_table(w, forms, steps, warmup, torch, oracle_obj, n_frames_err):
             "dft_mfma_frac": round(flops * MFMA_FLOP_MULT[form] / (dft_ms * 1e-3) / 1e12 / PEAK_TFLOPS[form], 4),
         }
         res[entry].update(channel_errors(got, ref, w, fr))
-        # FIR stage bytes: FP32 input once, output FP32 (or 1 + 1/32 bytes per
-        # float in the block-scaled form, which the FIR writes directly).
-        fir_out_b = (1.0 + 1.0 / 32) if form == "mxfp8" else 4.0
+        # FIR stage bytes: FP32 input once, and the GEMM operand it writes per
+        # float (FP32 rows, or the reduced form's codes; the per-frame scaled
+        # forms' second input pass is not counted: it is not algorithmic).
+        fir_out_b = FIR_OUT_BYTES[form]
         fir_b = F * w.P * (2 if w.complex_input else 1) * (4.0 + fir_out_b)
         res[entry]["fir_hbm_gbs"] = round(fir_b / (fir_ms * 1e-3) / 1e9, 1)
         if dft == "factored":   # the dense-DFT flop figures do not apply

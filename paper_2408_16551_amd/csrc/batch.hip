@@ -239,8 +239,6 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.lda = p->W;
         ga.B0 = p->B[0];
         ga.B1 = p->B[1];
-        ga.amax = fa.amax;
-        ga.nparts = fa.nparts;
         ga.out = (float*)it.d_out;
         ga.ldo = p->cf == 2 ? 2 * (int64_t)p->P : (int64_t)p->P + 2;
         ga.F = F;
@@ -319,7 +317,7 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     const int qmode = form_fir_qmode(b->form);
     if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, form_scaled(b->form), qmode, grid_fir, s));
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, qmode, grid_fir, s));
     if (always || b->h_table->gemm_units > 0)
         HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));

@@ -169,12 +169,10 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
     if (a.qmode == QM_MX) return launch_fir_mode_mx(a, vec, s);
     if (a.qmode == QM_BF16) return launch_fir_mode_bf16(a, vec, s);
     if (a.qmode == QM_BF16X2) return launch_fir_mode_bf16x2(a, vec, s);
-    if (a.amax) return launch_fir_mode_amax(a, vec, s);
     return launch_fir_mode_f32(a, vec, s);
 }
 
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
-                            hipStream_t s) {
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s) {
     if (qmode_frame_scaled(qmode)) {  // as in launch_fir: maxima, exponents, codes
         hipError_t e = launch_fir_batch_mode_amaxonly(t, max_m, all_exact, grid, s);
         if (e != hipSuccess) return e;
@@ -190,7 +188,6 @@ hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool
     if (qmode == QM_MX) return launch_fir_batch_mode_mx(t, max_m, all_exact, grid, s);
     if (qmode == QM_BF16) return launch_fir_batch_mode_bf16(t, max_m, all_exact, grid, s);
     if (qmode == QM_BF16X2) return launch_fir_batch_mode_bf16x2(t, max_m, all_exact, grid, s);
-    if (amax) return launch_fir_batch_mode_amax(t, max_m, all_exact, grid, s);
     return launch_fir_batch_mode_f32(t, max_m, all_exact, grid, s);
 }
 

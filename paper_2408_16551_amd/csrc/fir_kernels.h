@@ -12,8 +12,8 @@
 namespace tina {
 
 // Output modes of the FIR: FP32 rows, FP32 rows plus per-frame partial
-// maxima (per-frame scaled forms), block-scaled FP8 codes and scales, bf16
-// pieces, partial maxima alone, per-frame scaled FP8 or fp16 pieces.
+// maxima (no path instantiates it now), block-scaled FP8 codes and scales,
+// bf16 pieces, partial maxima alone, per-frame scaled FP8 or fp16 pieces.
 enum FirOut : int {
     FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4,
     FIR_OUT_AMAXONLY = 5, FIR_OUT_FP8F = 6, FIR_OUT_FP16F = 7, FIR_OUT_FP16FX2 = 8
@@ -50,7 +50,6 @@ int pick_vec(const FirArgs& a);
 
 // Per-mode entry points (fir_out_*.hip).
 hipError_t launch_fir_mode_f32(FirArgs& a, int vec, hipStream_t s);
-hipError_t launch_fir_mode_amax(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_mx(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_bf16(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_bf16x2(FirArgs& a, int vec, hipStream_t s);
@@ -59,7 +58,6 @@ hipError_t launch_fir_mode_fp8f(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_fp16f(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_fp16fx2(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_batch_mode_f32(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
-hipError_t launch_fir_batch_mode_amax(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_mx(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_bf16(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);
 hipError_t launch_fir_batch_mode_bf16x2(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s);

@@ -39,9 +39,6 @@ template <> struct FT<FORM_BF16X3> { static constexpr int EB = 2, NP = 2, SLAB =
 template <> struct FT<FORM_FP16> { static constexpr int EB = 2, NP = 1, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
 template <> struct FT<FORM_FP16X3> { static constexpr int EB = 2, NP = 2, SLAB = 32; static constexpr bool SCALED = true, MX = false; };
 template <> struct FT<FORM_FP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = true, MX = false; };
-// Operand bytes per row and K tile in the converting tile: 128, or 64 for FP8
-// (its FP32 A prefetch would otherwise hold 64 registers per lane).
-template <int FORM> constexpr int kRowB = FORM == FORM_FP8 ? 64 : 128;
 template <> struct FT<FORM_MXFP8> { static constexpr int EB = 1, NP = 1, SLAB = 64; static constexpr bool SCALED = false, MX = true; };
 
 constexpr int BM = 128;               // block tile rows (frames); columns BN = 64 * WN
@@ -136,10 +133,8 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 
 template <int FORM, int WN>
 struct GemmSmem {
-    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN, RSF = kRowB<FORM> + 16;
-    uint8_t tiles[NP * (BM + BN) * RSF];  // NP A pieces (BM rows), then NP B pieces (BN rows), RSF bytes a row
-    float inv[BM], sc[BM];               // per-frame scale and its inverse
-    uint32_t mxs[FT<FORM>::MX ? BM + BN : 1];  // block scales of the K tile: 4 bytes per A row, then B row
+    static constexpr int NP = FT<FORM>::NP, BN = 64 * WN;
+    uint8_t tiles[NP * (BM + BN) * RS];  // NP A pieces (BM rows), then NP B pieces (BN rows), RS bytes a row
 };
 
 // Map a logical tile index L of an nm x nn grid: groups of GROUP_M m-tiles
@@ -208,13 +203,18 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int
 
 
 // One BM x BN output tile at (m0, n0), BN = 64 * WN: 2 x 2 waves, each
-// 64 x 32 WN as 2 x WN MFMA blocks.  Called by every thread of the block.
+// 64 x 32 WN as 2 x WN MFMA blocks, with A read as FP32 rows: FP32, and bf16
+// (one piece, or hi + lo) converted while it is staged (the synthesis bank's
+// inverse DFT takes its FP32 channel frames this way).  The analysis bank's
+// reduced forms take A in operand form from the FIR (gemm_tile_raw).  Called
+// by every thread of the block.
 template <int FORM, int WN>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM, WN>& sm) {
     constexpr int BN = 64 * WN, WC = 32 * WN;  // block tile columns, columns per wave
     using ft = FT<FORM>;
+    static_assert(FORM == FORM_FP32 || FORM == FORM_BF16 || FORM == FORM_BF16X3, "FP32 A, converted to bf16 at most");
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
-    constexpr int ROWB = kRowB<FORM>, RS = ROWB + 16, CPR = ROWB / 16;  // 16-byte chunks per row
+    constexpr int CPR = ROWB / 16;                // 16-byte chunks per row
     constexpr int BK = ROWB / EB;                 // K elements per tile
     constexpr int ACPR = BK / 4;                  // A float4 chunks per row
     constexpr int ACH = BM * ACPR / NT;           // A float4 chunks per thread (FP32 A)
@@ -224,8 +224,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 
     uint8_t* As = sm.tiles;                 // NP pieces of BM x RS
     uint8_t* Bs = sm.tiles + NP * BM * RS;  // NP pieces of BN x RS
-    float* s_inv = sm.inv;
-    float* s_sc = sm.sc;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -233,20 +231,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 
     __syncthreads();  // the previous tile of a persistent block is done with LDS
 
-    if constexpr (ft::SCALED) {
-        if (tid < BM) {
-            const int64_t f = m0 + tid;
-            float amax = 0.0f;
-            if (f < g.F)
-                for (int q = 0; q < g.nparts; ++q) amax = fmaxf(amax, g.amax[f * g.nparts + q]);
-            const int e = frame_exponent(amax, FORM == FORM_FP8 ? 448.0f : 32768.0f);
-            s_inv[tid] = ldexpf(1.0f, -e);
-            s_sc[tid] = ldexpf(1.0f, e);
-        }
-        __syncthreads();
-    }
-
-    static_assert(!ft::MX, "the block-scaled form takes the raw-operand tile");
     float4 ra[ACH];
     uint4 rb[NP][BCH];
     const uint8_t* Bp[2] = {(const uint8_t*)g.B0, (const uint8_t*)g.B1};
@@ -288,22 +272,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                     const float lz = x.z - bf16_round(x.z), lw = x.w - bf16_round(x.w);
                     *reinterpret_cast<uint2*>(dst0 + BM * RS) = make_uint2(bf16_pair(lx, ly), bf16_pair(lz, lw));
                 }
-            } else if constexpr (FORM == FORM_FP16 || FORM == FORM_FP16X3) {
-                const float s = s_inv[row];
-                const float x0 = x.x * s, x1 = x.y * s, x2 = x.z * s, x3 = x.w * s;
-                *reinterpret_cast<uint2*>(dst0) = make_uint2(f16_pair(x0, x1), f16_pair(x2, x3));
-                if constexpr (FORM == FORM_FP16X3) {
-                    const float l0 = (x0 - f16_round(x0)) * 2048.0f, l1 = (x1 - f16_round(x1)) * 2048.0f;
-                    const float l2 = (x2 - f16_round(x2)) * 2048.0f, l3 = (x3 - f16_round(x3)) * 2048.0f;
-                    *reinterpret_cast<uint2*>(dst0 + BM * RS) = make_uint2(f16_pair(l0, l1), f16_pair(l2, l3));
-                }
-            } else {
-                const float s = s_inv[row];
-                const float x0 = fminf(fmaxf(x.x * s, -448.f), 448.f), x1 = fminf(fmaxf(x.y * s, -448.f), 448.f);
-                const float x2 = fminf(fmaxf(x.z * s, -448.f), 448.f), x3 = fminf(fmaxf(x.w * s, -448.f), 448.f);
-                int w = __builtin_amdgcn_cvt_pk_fp8_f32(x0, x1, 0, false);
-                w = __builtin_amdgcn_cvt_pk_fp8_f32(x2, x3, w, true);
-                *reinterpret_cast<int*>(dst0) = w;
             }
         }
 #pragma unroll
@@ -361,7 +329,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         }
     }
 
-    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, s_sc);
+    gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, nullptr);
 }
 
 // FIR fused into the FP32 GEMM: the A tile of K tile t (frames m0.., K
@@ -783,15 +751,8 @@ hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n
         }
         return hipGetLastError();
     }
-    switch (form) {
-        case FORM_FP32: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP32, false>), gd, bd, 0, s, t); break;
-        case FORM_BF16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16, false>), gd, bd, 0, s, t); break;
-        case FORM_BF16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_BF16X3, false>), gd, bd, 0, s, t); break;
-        case FORM_FP16: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16, false>), gd, bd, 0, s, t); break;
-        case FORM_FP16X3: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP16X3, false>), gd, bd, 0, s, t); break;
-        case FORM_FP8: hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP8, false>), gd, bd, 0, s, t); break;
-        default: return hipErrorInvalidValue;
-    }
+    if (form != FORM_FP32) return hipErrorInvalidValue;  // the other forms take A in operand form
+    hipLaunchKernelGGL((dft_gemm_batch_kernel<FORM_FP32, false>), gd, bd, 0, s, t);
     return hipGetLastError();
 }
 
@@ -838,10 +799,7 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
         case FORM_FP32: return launch_form<FORM_FP32>(g, s);
         case FORM_BF16: return launch_form<FORM_BF16>(g, s);
         case FORM_BF16X3: return launch_form<FORM_BF16X3>(g, s);
-        case FORM_FP16: return launch_form<FORM_FP16>(g, s);
-        case FORM_FP16X3: return launch_form<FORM_FP16X3>(g, s);
-        case FORM_FP8: return launch_form<FORM_FP8>(g, s);
-        default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;  // the others take A in operand form
     }
 }
 

@@ -90,17 +90,15 @@ struct GemmArgs {
     int64_t lda;
     const void* B0;        // Bt piece 0 [N][K]
     const void* B1;        // Bt piece 1 (split forms)
-    const float* amax;     // per-frame partial maxima [F][nparts] (scaled forms)
-    int32_t nparts;
     float* out;            // output rows (floats), row stride ldo
     int64_t ldo;
     int64_t F;
     int32_t K, N;
     int32_t real_pack;     // real input: column 0 -> X_0, column 1 -> X_{P/2}, rest in place
     int32_t form;
-    // A already in operand form (raw-operand forms; nullptr: FP32 A above,
-    // converted in the tile): piece 0 / piece 1 [F][lda elements], and for
-    // FORM_MXFP8 the E8M0 scales [F][K/32] (then B0/B1 = Bt codes / scales).
+    // A in operand form (every form but FP32, whose A is the FP32 rows
+    // above): piece 0 / piece 1 [F][lda elements], and for FORM_MXFP8 the
+    // E8M0 scales [F][K/32] (then B0/B1 = Bt codes / scales).
     const uint8_t* Aq;
     const uint8_t* Aq1;
     const uint8_t* Aqs;
@@ -178,8 +176,7 @@ constexpr int kGemmBM = 128, kGemmBN = 128;
 
 // Per-frame scaled qmodes run three launches: partial maxima, per-frame
 // exponents, scaled codes.
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, bool amax, int qmode, int grid,
-                             hipStream_t s);
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s);
 // FirArgs::qmode the FIR writes for a DFT form (0: FP32 y): every form but
 // FP32 takes its operand straight from the FIR.
 inline int form_fir_qmode(int form) {

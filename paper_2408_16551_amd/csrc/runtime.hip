@@ -314,8 +314,6 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             ga.lda = p->W;
             ga.B0 = p->B[0];
             ga.B1 = p->B[1];
-            ga.amax = fa.amax;
-            ga.nparts = fa.nparts;
             ga.out = (float*)d_out + c0 * ldo;
             ga.ldo = ldo;
             ga.F = Fc;
