@@ -137,7 +137,7 @@ def test_pfb_reduced_precision_within_stated_bound(oracle, P, M, N, cplx, window
     assert err < REDUCED_BOUNDS[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp8"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp8", "fp16", "fp16x3"])
 @pytest.mark.parametrize("P,M,cplx", [(16, 4, False), (1024, 16, True), (64, 9, False)])
 def test_streaming_chunked_equals_one_shot_bitwise(oracle, P, M, cplx, precision):
     from paper_2408_16551_amd.pfb import State
@@ -157,6 +157,34 @@ def test_streaming_chunked_equals_one_shot_bitwise(oracle, P, M, cplx, precision
         s = Stream(oracle, P, M, oracle.window(P, M, "hann"), cplx)
         ref = np.concatenate([s.push(x[a:b]) for a, b in zip(cuts[:-1], cuts[1:])])
         assert rel_l2(got, ref) < FP32_BOUND
+
+
+@pytest.mark.parametrize("precision", ["fp8", "fp16", "fp16x3"])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_per_frame_scale_follows_each_frame(oracle, precision, cplx):
+    # Blocks of frames at scales 40 decades apart, and all-zero blocks: each
+    # frame takes its own power-of-two scale, so every block keeps the form's
+    # relative error, and frames whose whole window is zero come out exactly
+    # zero (a zero maximum takes exponent 0).
+    P, M, B = 256, 8, 24                     # channels, taps, frames per block
+    scales = [1.0, 0.0, 1e-20, 1e20, 3e-5, 0.0, 7e10, 1.0]
+    g = np.random.Generator(np.random.PCG64(77))
+    x = np.concatenate([s * g.standard_normal(P * B) for s in scales])
+    if cplx:
+        x = x + 1j * np.concatenate([s * g.standard_normal(P * B) for s in scales])
+        x = x.astype(np.complex64)
+    else:
+        x = x.astype(np.float32)
+    plan = _plan(P, M, cplx, precision=precision)
+    got = _run(plan, x)
+    ref = oracle.pfb(x, P, M, oracle.window(P, M, "hann"))
+    bound = {"fp8": 0.1, "fp16": 1e-3, "fp16x3": 2e-6}[precision]
+    for b, s in enumerate(scales):
+        rows = slice(b * B + M - 1, (b + 1) * B)   # frames whose window lies in block b
+        if s == 0.0:
+            assert np.all(got[rows] == 0)
+        else:
+            assert rel_l2(got[rows], ref[rows]) < bound, (b, s)
 
 
 @pytest.mark.parametrize("cplx", [False, True])
