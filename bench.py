@@ -402,6 +402,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     sid_seq = g.integers(0, len(streams), size=N)
     len_seq = lens(N)
     lat, blocked = [None] * N, [0]
+    parts = [None] * N   # (submit lag, admission wait, wait for the first step, steps until done), ms
     done_ids = []
     base = sv.stats()["now_us"] * 1e-6 - time.perf_counter()   # server clock - host clock
 
@@ -409,6 +410,9 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
         for i, rid, oi in iter(q.get, None):
             r = sv.wait(rid)
             lat[i] = (r["t_done_us"] * 1e-6 - (arrivals[i] + t_start + base)) * 1e3
+            parts[i] = ((r["t_submit_us"] * 1e-6 - (arrivals[i] + t_start + base)) * 1e3,
+                        (r["t_admit_us"] - r["t_submit_us"]) * 1e-3, (r["t_first_step_us"] - r["t_admit_us"]) * 1e-3,
+                        (r["t_done_us"] - r["t_first_step_us"]) * 1e-3, r["steps"])
             with lock:
                 free_out.append(oi)
                 lock.notify_all()
@@ -440,16 +444,22 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     st = sv.stats()
     sv.close()
     m = np.array(lat[n_warm:], dtype=np.float64)
+    pa = np.array(parts[n_warm:], dtype=np.float64)
+    breakdown = {name: {"p50": round(float(np.percentile(pa[:, j], 50)), 3), "p99": round(float(np.percentile(pa[:, j], 99)), 3)}
+                 for j, name in enumerate(("submit_lag_ms", "admission_ms", "to_first_step_ms", "steps_ms", "steps"))}
     return {"precision": precision, "hbm_budget_bytes": budget_bytes, "rho": rho,
             "buffers": "device (in place)" if device else "host (pinned; copied in and out)",
             "frames_per_step": frames_per_step,
             "capacity_gsps_closed_burst": round(cap / 1e9, 3), "rate_req_per_s": round(lam, 1),
             "mean_request_samples": round(mean_len), "requests_measured": n_meas, "warmup_requests": n_warm,
             "p50_ms": round(float(np.percentile(m, 50)), 3), "p99_ms": round(float(np.percentile(m, 99)), 3),
+            # the same from the submit call (leaves out the client's own lag behind the schedule)
+            "p50_ms_from_submit": round(float(np.percentile(m - pa[:, 0], 50)), 3),
+            "p99_ms_from_submit": round(float(np.percentile(m - pa[:, 0], 99)), 3),
             "mean_ms": round(float(m.mean()), 3), "gsps_served": round(samples_meas / t_total / 1e9, 3),
             "admission_waits": st["admission_waits"], "steps": st["steps"],
             "device_busy_frac": round(st["device_busy_ms"] / (st["now_us"] / 1e3), 3),
-            "submitter_blocked_on_output_buffers": blocked[0]}
+            "submitter_blocked_on_output_buffers": blocked[0], "latency_parts": breakdown}
 
 
 def main():

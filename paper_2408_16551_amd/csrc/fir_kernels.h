@@ -507,7 +507,10 @@ __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __rest
     for (int64_t u = t->fir_bounds[x] + i; u < end; u += nbx) {
         const int it = batch_find(t->items, t->n_items, u, /*stage=*/0);
         const BatchItem& b = t->items[it];
-        fir_unit<1, MT, EXACT, AMAX, true, QM>(b.fir, b.fir_tf, u - b.fir_unit0);
+        // A private copy of the item's arguments: read through the table, every
+        // field would be reloaded after each output store (they might alias).
+        const FirArgs fa = b.fir;
+        fir_unit<1, MT, EXACT, AMAX, true, QM>(fa, b.fir_tf, u - b.fir_unit0);
     }
 }
 
