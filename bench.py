@@ -421,6 +421,9 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     q = _q.Queue()
     th = threading.Thread(target=collector, args=(q,), daemon=True)
     th.start()
+    import gc
+    gc.collect()
+    gc.disable()   # no collector pauses in the submitting loop (they would count as latency)
     t_start = time.perf_counter()
     samples_meas = 0
     for i in range(N):
@@ -440,6 +443,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
             samples_meas += int(len_seq[i])
     q.put(None)
     th.join()
+    gc.enable()
     t_total = time.perf_counter() - t_start - arrivals[n_warm - 1] if n_warm else time.perf_counter() - t_start
     st = sv.stats()
     sv.close()
