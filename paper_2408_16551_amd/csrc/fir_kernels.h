@@ -557,7 +557,23 @@ hipError_t launch_one(FirArgs& a, hipStream_t s) {
 
 template <int VEC, int MT, int MODE>
 hipError_t launch_mt(FirArgs& a, hipStream_t s) {
-    return a.M == MT ? launch_one<VEC, MT, true, MODE>(a, s) : launch_one<VEC, MT, false, MODE>(a, s);
+    if (a.M == MT) return launch_one<VEC, MT, true, MODE>(a, s);
+    // 9..15 taps at 1 or 2 floats per thread: the ring unrolled for the
+    // exact count (the run-time predicated form takes 2.5x the registers);
+    // at 4 floats per thread the 8-frame load groups need MT % 8 == 0.
+    if constexpr (MT == 16 && VEC <= 2) {
+        switch (a.M) {
+            case 9: return launch_one<VEC, 9, true, MODE>(a, s);
+            case 10: return launch_one<VEC, 10, true, MODE>(a, s);
+            case 11: return launch_one<VEC, 11, true, MODE>(a, s);
+            case 12: return launch_one<VEC, 12, true, MODE>(a, s);
+            case 13: return launch_one<VEC, 13, true, MODE>(a, s);
+            case 14: return launch_one<VEC, 14, true, MODE>(a, s);
+            case 15: return launch_one<VEC, 15, true, MODE>(a, s);
+            default: break;
+        }
+    }
+    return launch_one<VEC, MT, false, MODE>(a, s);
 }
 
 template <int VEC, int MODE>

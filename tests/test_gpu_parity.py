@@ -77,7 +77,8 @@ def test_fir_impulse_gives_fp32_taps_exactly(oracle, P, M, f0, p0, cplx):
 
 FIR_SHAPES = [(16, 4, 1 << 16, False), (64, 5, 64 * 37 + 11, True), (1024, 16, 1024 * 40 + 3, False),
               (256, 17, 256 * 50 + 100, True), (16, 33, 16 * 90 + 1, False), (32, 64, 32 * 140, True),
-              (16, 1, 16 * 20, False), (4096, 8, 4096 * 20 + 4095, True), (128, 3, 127, False)]
+              (16, 1, 16 * 20, False), (4096, 8, 4096 * 20 + 4095, True), (128, 3, 127, False),
+              (128, 12, 128 * 60 + 5, True), (512, 15, 512 * 33, False)]
 
 
 @pytest.mark.parametrize("P,M,N,cplx", FIR_SHAPES)
@@ -96,7 +97,7 @@ PFB_SHAPES = [(16, 4, 1 << 16, False, "hann"), (64, 5, 64 * 300 + 11, True, "ham
               (1024, 16, 1024 * 300 + 77, False, "hann"), (256, 16, 256 * 260 + 5, True, "hann"),
               (4096, 8, 4096 * 140 + 1000, True, "blackman"), (32, 33, 32 * 200, False, "blackman"),
               (16, 1, 16 * 130, True, "rect"), (8192, 2, 8192 * 20, False, "hann"),
-              (2048, 64, 2048 * 70, True, "hann")]
+              (2048, 64, 2048 * 70, True, "hann"), (512, 11, 512 * 90 + 7, False, "hamming")]
 
 
 @pytest.mark.parametrize("P,M,N,cplx,window", PFB_SHAPES)
