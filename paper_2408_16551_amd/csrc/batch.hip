@@ -190,7 +190,12 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
     const int MT = pow2_at_least(max_m);
     all_exact = true;
     for (int i = 0; i < g.count; ++i) all_exact = all_exact && w[g.first + i].plan->M == MT;
-    const int TF = tune.fir_tf_mult * MT < 16 ? ((16 + MT - 1) / MT) * MT : tune.fir_tf_mult * MT;
+    // Frames per FIR thread, a whole number of the unit's ring blocks: the
+    // ring is MT frames long, or the item's own M when mixed tap counts up to
+    // 16 run per-M units.
+    auto frames_per_thread = [&](int ring) {
+        return tune.fir_tf_mult * ring < 16 ? ((16 + ring - 1) / ring) * ring : tune.fir_tf_mult * ring;
+    };
 
     std::vector<int64_t> fu(g.count), gu(g.count), su(g.count);
     std::vector<double> fc(g.count), gc(g.count), sc(g.count, 1.0);
@@ -250,10 +255,12 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.Aq1 = fa.q1;
         ga.Aqs = fa.qs;
         ga.fexp = fa.fexp;
+        const int ring = (!all_exact && MT <= 16) ? p->M : MT;
+        const int TF = frames_per_thread(ring);
         bi.fir_tf = TF;
         const int64_t runs = (F + TF - 1) / TF;
         fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
-        fc[i] = (double)TF * MT;
+        fc[i] = (double)TF * ring;
         gu[i] = F > 0 ? ((F + kGemmBM - 1) / kGemmBM) * ((p->N + tune.gemm_tile_n - 1) / tune.gemm_tile_n) : 0;
         gc[i] = (double)p->K;
         bi.fir_unit0 = f0;
@@ -324,6 +331,34 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     return TINA_OK;
 }
 
+// The captured step graph of one kernel variant (tap ring, exact taps,
+// launch shape), captured and instantiated on first use.
+tina_status step_graph(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
+                       hipGraphExec_t& exec) {
+    const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
+                            std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipMemcpyAsync(b->d_table, b->h_table, b->table_bytes, hipMemcpyHostToDevice, s);
+        tina_status st =
+            e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid) : TINA_ERR_DEVICE;
+        hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess || st != TINA_OK || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(TINA_ERR_DEVICE, "batch: step graph capture failed");
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(TINA_ERR_DEVICE, std::string("batch: graph instantiate: ") + hipGetErrorString(e));
+        it = b->graphs.emplace(key, ex).first;
+    }
+    exec = it->second;
+    return TINA_OK;
+}
+
 tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, const Tune& tune, bool dry,
                       const std::vector<int64_t>& frames, bool use_graph = false) {
     const std::vector<GroupPlan> groups = make_groups(b, w, frames, n);
@@ -341,27 +376,10 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
             // Fixed topology: the full-size table upload and all three launches
             // (a stage with no units returns at once), so one graph per kernel
             // variant serves every step.
-            const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
-                                    std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
-            auto it = b->graphs.find(key);
-            if (it == b->graphs.end()) {
-                hipGraph_t graph = nullptr;
-                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                hipError_t e = hipMemcpyAsync(b->d_table, b->h_table, b->table_bytes, hipMemcpyHostToDevice, s);
-                tina_status st =
-                    e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid) : TINA_ERR_DEVICE;
-                hipError_t e2 = hipStreamEndCapture(s, &graph);
-                if (e != hipSuccess || st != TINA_OK || e2 != hipSuccess) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return fail(TINA_ERR_DEVICE, "batch: step graph capture failed");
-                }
-                hipGraphExec_t exec = nullptr;
-                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (e != hipSuccess) return fail(TINA_ERR_DEVICE, std::string("batch: graph instantiate: ") + hipGetErrorString(e));
-                it = b->graphs.emplace(key, exec).first;
-            }
-            HIP_TRY(hipGraphLaunch(it->second, s));
+            hipGraphExec_t exec = nullptr;
+            tina_status st = step_graph(b, s, tune, max_m, all_exact, exec);
+            if (st != TINA_OK) return st;
+            HIP_TRY(hipGraphLaunch(exec, s));
         } else {
             HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
             tina_status st = launch_stages(b, s, tune, max_m, all_exact, false);
@@ -417,14 +435,30 @@ tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hi
     tina_status st = validate(b, w, n, frames);
     if (st != TINA_OK) return st;
     DeviceScope ds(b->device);
-    Tune tune;
-    {
+    Tune tune;  // graph steps keep the default launch shape: their graphs are captured in advance
+    if (!use_graph) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune_cache.find(signature(b, w, frames, n));
         if (it != g_tune_cache.end()) tune = it->second;
     }
     return run_batch(b, w, n, s, tune, false, frames, use_graph);
+}
+
+// Used by the server at creation: captures the step graph of every tap-ring
+// variant (largest tap count 1..64, exact or mixed) with the default launch
+// shape, so that no capture is ever in progress while the server runs: HIP
+// refuses a device-wide synchronize from any thread during a capture.
+tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s) {
+    DeviceScope ds(b->device);
+    const Tune tune;
+    for (int mt = 1; mt <= 64; mt *= 2)
+        for (int exact = 1; exact >= (mt == 1 ? 1 : 0); --exact) {
+            hipGraphExec_t exec = nullptr;
+            tina_status st = step_graph(b, s, tune, mt, exact != 0, exec);
+            if (st != TINA_OK) return st;
+        }
+    return TINA_OK;
 }
 
 extern "C" {

@@ -511,8 +511,8 @@ __device__ __forceinline__ void fir_unit_own_m(const FirArgs& a, int TF, int64_t
 
 // Persistent batched FIR: each block walks its XCD's contiguous, cost-balanced
 // range of units (see BatchTable); a unit is one 256-thread block of one item.
-// Batches whose largest tap count is 9..16 with mixed tap counts run every
-// item's units with the ring unrolled for its own M.
+// Batches whose largest tap count is at most 16 with mixed tap counts run
+// every item's units with the ring unrolled for its own M.
 template <int MT, bool EXACT, bool AMAX, int QM>
 __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __restrict__ t) {
     const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __rest
         // A private copy of the item's arguments: read through the table, every
         // field would be reloaded after each output store (they might alias).
         const FirArgs fa = b.fir;
-        if constexpr (!EXACT && MT == 16) fir_unit_own_m<1, MT, AMAX, QM>(fa, b.fir_tf, u - b.fir_unit0);
+        if constexpr (!EXACT && MT <= 16) fir_unit_own_m<1, MT, AMAX, QM>(fa, b.fir_tf, u - b.fir_unit0);
         else fir_unit<1, MT, EXACT, AMAX, true, QM>(fa, b.fir_tf, u - b.fir_unit0);
     }
 }
@@ -536,7 +536,9 @@ hipError_t launch_one(FirArgs& a, hipStream_t s) {
     // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
     // least 16) keeps the halo re-reads in L2 while leaving enough waves to
     // hide HBM latency.
-    int TF = 2 * MT < 16 ? 16 : 2 * MT;
+    // A multiple of MT, so that every run is whole ring blocks (tap counts
+    // that are not powers of two included).
+    int TF = 2 * MT < 16 ? ((16 + MT - 1) / MT) * MT : 2 * MT;
     const FirTune tune = fir_tune();
     if (tune.tf > 0) TF = ((tune.tf + MT - 1) / MT) * MT;
     const int64_t runs = (a.F + TF - 1) / TF;
@@ -572,6 +574,17 @@ hipError_t launch_mt(FirArgs& a, hipStream_t s) {
             case 15: return launch_one<VEC, 15, true, MODE>(a, s);
             default: break;
         }
+    }
+    if constexpr (MT == 8) {  // 5..7 taps (8-frame load groups hold the whole ring at any width)
+        switch (a.M) {
+            case 5: return launch_one<VEC, 5, true, MODE>(a, s);
+            case 6: return launch_one<VEC, 6, true, MODE>(a, s);
+            case 7: return launch_one<VEC, 7, true, MODE>(a, s);
+            default: break;
+        }
+    }
+    if constexpr (MT == 4) {
+        if (a.M == 3) return launch_one<VEC, 3, true, MODE>(a, s);
     }
     return launch_one<VEC, MT, false, MODE>(a, s);
 }

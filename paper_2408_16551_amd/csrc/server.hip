@@ -367,6 +367,11 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
         hipStreamCreateWithFlags(&sv->s_d2h, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&sv->ev_a) != hipSuccess || hipEventCreate(&sv->ev_b) != hipSuccess)
         return bail(TINA_ERR_DEVICE, "server_create: streams/events");
+    if (c->use_graph) {  // every step graph now, none while requests run
+        st = batch_prepare_graphs(sv->batch, sv->s_comp);
+        if (st == TINA_OK && hipStreamSynchronize(sv->s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+        if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
+    }
     sv->th = std::thread([sv] { sv->loop(); });
     *out = sv;
     return TINA_OK;

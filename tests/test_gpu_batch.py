@@ -57,6 +57,30 @@ def test_batch_equals_single_execute_bitwise(precision):
         assert torch.equal(o[:f], single)
 
 
+# Largest tap count 8 with mixed counts: every item runs the ring unrolled for
+# its own M (1..8), which must give the single path's bits and the oracle's values.
+SMALL_M_MIX = [(64, 3, True, 64 * 90 + 7), (128, 5, False, 128 * 70), (256, 7, True, 256 * 41 + 3),
+               (32, 8, False, 32 * 200), (16, 1, True, 16 * 64), (512, 6, False, 512 * 20 + 100)]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp8", "bf16x3"])
+def test_batch_small_tap_counts_bitwise_and_oracle(oracle, precision):
+    from paper_2408_16551_amd.pfb import Batch
+    plans, xs, outs = _items(SMALL_M_MIX, precision, seed=300)
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    b = Batch(precision, max_items=16, workspace_bytes=256 << 20)
+    fw = b.execute([(p, x, o) for p, x, o in zip(plans, xd, outs)])
+    torch.cuda.synchronize()
+    for (P, M, cplx, N), p, x, xh, o, f in zip(SMALL_M_MIX, plans, xd, xs, outs, fw):
+        single = p(x)
+        torch.cuda.synchronize()
+        assert f == single.shape[0]
+        assert torch.equal(o[:f], single)
+        if precision == "fp32":
+            ref = oracle.pfb(xh[: (N // P) * P], P, M, oracle.window(P, M, "hann"))
+            assert rel_l2(o[:f].cpu().numpy(), ref) < 1e-5
+
+
 def test_batch_fp32_matches_oracle(oracle):
     from paper_2408_16551_amd.pfb import Batch
     plans, xs, outs = _items(MIX, "fp32", seed=100)
