@@ -37,7 +37,8 @@ int pick_vec(const FirArgs& a) {
     // Block-scaled output: 4 floats per thread up to 16 taps (the per-block
     // maximum is then shared among 8 lanes, and a lane's 4 codes leave in one
     // store; measured faster than 1 or 2 at 16 taps).
-    if ((a.qmode == QM_MX || a.qmode == QM_FP8F) && a.M <= 16) vec = 4;
+    // (9..15 taps take 2, whose ring can be unrolled for the exact count.)
+    if ((a.qmode == QM_MX || a.qmode == QM_FP8F) && a.M <= 16) vec = (a.M <= 8 || a.M == 16) ? 4 : 2;
     const FirTune tune = fir_tune();
     if (tune.vec == 1 || tune.vec == 2 || tune.vec == 4) vec = tune.vec;
     if (vec == 4 && a.M > 16) vec = 2;  // widest ring per vector width: 16 taps (VEC 4), 32 (VEC 2), 64 (VEC 1)

@@ -79,7 +79,7 @@ def test_identity_fir_matches_oracle_block_scaled_dft(oracle, P, cplx, F):
 
 
 @pytest.mark.parametrize("P,M,cplx,F,window", [(256, 8, True, 300, "blackman"), (1024, 16, False, 200, "hann"),
-                                               (128, 5, False, 129, "hamming")])
+                                               (128, 5, False, 129, "hamming"), (512, 12, True, 150, "hann")])
 def test_pfb_matches_oracle_block_scaled_dft_of_fir(oracle, P, M, cplx, F, window):
     x = _ranged(P * F + 7, cplx, seed=3 * P + M, seg=64, decades=2)
     X = _run(_plan(P, M, cplx, window=window), x)
