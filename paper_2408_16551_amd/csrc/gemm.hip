@@ -665,8 +665,11 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     gemm_tile<FORM, WN>(g, m0, n0, sm);
 }
 
+// Held to 2 waves per SIMD: the fp16 hi + lo form with its second accumulator
+// otherwise took 331 registers and one wave (2 waves with 4 spilled registers
+// measured 10-20% faster); the other forms fit 2 waves anyway.
 template <int FORM, int WN>
-__global__ __launch_bounds__(NT) void dft_gemm_raw_kernel(GemmArgs g) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void dft_gemm_raw_kernel(GemmArgs g) {
     constexpr int BN = 64 * WN;
     __shared__ __attribute__((aligned(16))) RawSmem<FORM, WN> sm;
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
