@@ -11,11 +11,11 @@
 
 namespace tina {
 
-// Output modes of the FIR: FP32 rows, FP32 rows plus per-frame partial
-// maxima (no path instantiates it now), block-scaled FP8 codes and scales,
-// bf16 pieces, partial maxima alone, per-frame scaled FP8 or fp16 pieces.
+// Output modes of the FIR: FP32 rows, block-scaled FP8 codes and scales,
+// bf16 pieces, per-frame partial maxima alone, per-frame scaled FP8 or fp16
+// pieces.
 enum FirOut : int {
-    FIR_OUT_F32 = 0, FIR_OUT_AMAX = 1, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4,
+    FIR_OUT_F32 = 0, FIR_OUT_MX = 2, FIR_OUT_BF16 = 3, FIR_OUT_BF16X2 = 4,
     FIR_OUT_AMAXONLY = 5, FIR_OUT_FP8F = 6, FIR_OUT_FP16F = 7, FIR_OUT_FP16FX2 = 8
 };
 // Operand-form output of the FIR (FirArgs::qmode): none (FP32 y), block-scaled
@@ -258,28 +258,26 @@ __device__ __forceinline__ typename VecT<VEC>::T buf_load(__amdgpu_buffer_rsrc_t
 // Per-frame partial maxima of |y| for the per-frame scaled forms: the gw
 // lanes (a power of two up to 32) that hold one part of a frame row reduce
 // their maxima with group_absmax, and the part's first lane stores it.
-template <int VEC, bool AMAX>
+template <int VEC>
 __device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
                                          int gw) {
-    if constexpr (AMAX) {
-        float mx = 0.0f;
+    float mx = 0.0f;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
-        switch (gw) {
-            case 32: mx = group_absmax<32>(mx); break;
-            case 16: mx = group_absmax<16>(mx); break;
-            case 8: mx = group_absmax<8>(mx); break;
-            case 4: mx = group_absmax<4>(mx); break;
-            case 2: mx = group_absmax<2>(mx); break;
-            default: break;
-        }
-        if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
+    for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(acc, v)));
+    switch (gw) {
+        case 32: mx = group_absmax<32>(mx); break;
+        case 16: mx = group_absmax<16>(mx); break;
+        case 8: mx = group_absmax<8>(mx); break;
+        case 4: mx = group_absmax<4>(mx); break;
+        case 2: mx = group_absmax<2>(mx); break;
+        default: break;
     }
+    if ((col & (gw - 1)) == 0) a.amax[f * a.nparts + col / gw] = mx;
 }
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
-// Store row u of a block: FP32 (plus the frame's partial maximum when AMAX),
+// Store row u of a block: FP32, the frame row's partial maxima only,
 // or an operand form (QM):
 //  - QM_MX, block-scaled FP8: the 32/VEC lanes that hold one 32-float block
 //    of the frame share its maximum (group_absmax), every lane converts its
@@ -289,7 +287,7 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) { return __builtin_bit_ca
 //  - QM_BF16 / QM_BF16X2: bf16 hi = RNE(y) (and lo = RNE(y - hi)), VEC
 //    values per lane.
 // f = the frame of row u.
-template <int VEC, bool AMAX, int QM, class Sink>
+template <int VEC, int QM, class Sink>
 __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<VEC>::T& acc, int64_t f, int col,
                                           int gw, const Sink& out, int u) {
     if constexpr (QM == QM_MX) {
@@ -354,7 +352,7 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
         put(0, hi);
         if constexpr (QM == QM_FP16FX2) put(1, lo);
     } else if constexpr (QM == QM_AMAXONLY) {
-        fir_amax<VEC, true>(a, acc, f, col, gw);
+        fir_amax<VEC>(a, acc, f, col, gw);
     } else if constexpr (QM == QM_BF16 || QM == QM_BF16X2) {
         uint32_t hi[4], lo[4];
 #pragma unroll
@@ -372,7 +370,6 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
         if constexpr (QM == QM_BF16X2) put(1, lo);
     } else {
         out.y(u, acc);
-        fir_amax<VEC, AMAX>(a, acc, f, col, gw);
     }
 }
 
@@ -380,7 +377,7 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
 // NT: non-temporal input loads and output stores (streaming cache policy);
 // QM: operand-form output (a.q, a.q1, a.qs; QMode) instead of FP32 (a.y).
 // One 256-thread unit of work: logical block `blk` of the (column, run) grid.
-template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, int QM>
+template <int VEC, int MT, bool EXACT, bool NT, int QM>
 __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) {
     using V = typename VecT<VEC>::T;
     const int ct = a.W / VEC;                    // threads per frame row (power of two)
@@ -479,33 +476,33 @@ __device__ __forceinline__ void fir_unit(const FirArgs& a, int TF, int64_t blk) 
                     const int u = sb + i;
                     win[u] = in[i];
                     const V acc = fir_point<VEC, MT, EXACT>(tp, win, u, M);
-                    fir_store<VEC, AMAX, QM>(a, acc, fb + u, col, gw, o, u);
+                    fir_store<VEC, QM>(a, acc, fb + u, col, gw, o, u);
                 }
             }
         } else {
             ring_ok = false;
             const PtrSink<VEC, NT> o = sink_ptr(fb);
-            for (int u = 0; u < MT; ++u) fir_store<VEC, AMAX, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
+            for (int u = 0; u < MT; ++u) fir_store<VEC, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
         }
     }
     // Tail block.
     const PtrSink<VEC, NT> o = sink_ptr(fb);
-    for (int u = 0; u < MT && fb + u < f_end; ++u) fir_store<VEC, AMAX, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
+    for (int u = 0; u < MT && fb + u < f_end; ++u) fir_store<VEC, QM>(a, direct(fb + u), fb + u, col, gw, o, u);
 }
 
-template <int VEC, int MT, bool EXACT, bool AMAX, bool NT, int QM>
+template <int VEC, int MT, bool EXACT, bool NT, int QM>
 __global__ __launch_bounds__(256) void fir_kernel(FirArgs a, int TF) {
-    fir_unit<VEC, MT, EXACT, AMAX, NT, QM>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
+    fir_unit<VEC, MT, EXACT, NT, QM>(a, TF, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 // One unit with the ring and tap loop unrolled for the item's own tap count
 // M0 (searched from M0 up to MT): the run-time predicated form of fir_unit
 // needs 2.5x the registers and runs 2-4x slower.  Same FMA order, same bits.
-template <int M0, int MT, bool AMAX, int QM>
+template <int M0, int MT, int QM>
 __device__ __forceinline__ void fir_unit_own_m(const FirArgs& a, int TF, int64_t blk) {
     if constexpr (M0 <= MT) {
-        if (a.M == M0) fir_unit<1, M0, true, AMAX, true, QM>(a, TF, blk);
-        else fir_unit_own_m<M0 + 1, MT, AMAX, QM>(a, TF, blk);
+        if (a.M == M0) fir_unit<1, M0, true, true, QM>(a, TF, blk);
+        else fir_unit_own_m<M0 + 1, MT, QM>(a, TF, blk);
     }
 }
 
@@ -513,7 +510,7 @@ __device__ __forceinline__ void fir_unit_own_m(const FirArgs& a, int TF, int64_t
 // range of units (see BatchTable); a unit is one 256-thread block of one item.
 // Batches whose largest tap count is at most 16 with mixed tap counts run
 // every item's units with the ring unrolled for its own M.
-template <int MT, bool EXACT, bool AMAX, int QM>
+template <int MT, bool EXACT, int QM>
 __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __restrict__ t) {
     const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
     const int64_t end = t->fir_bounds[x + 1];
@@ -523,14 +520,13 @@ __global__ __launch_bounds__(256) void fir_batch_kernel(const BatchTable* __rest
         // A private copy of the item's arguments: read through the table, every
         // field would be reloaded after each output store (they might alias).
         const FirArgs fa = b.fir;
-        if constexpr (!EXACT && MT <= 16) fir_unit_own_m<1, MT, AMAX, QM>(fa, b.fir_tf, u - b.fir_unit0);
-        else fir_unit<1, MT, EXACT, AMAX, true, QM>(fa, b.fir_tf, u - b.fir_unit0);
+        if constexpr (!EXACT && MT <= 16) fir_unit_own_m<1, MT, QM>(fa, b.fir_tf, u - b.fir_unit0);
+        else fir_unit<1, MT, EXACT, true, QM>(fa, b.fir_tf, u - b.fir_unit0);
     }
 }
 
 template <int VEC, int MT, bool EXACT, int MODE>
 hipError_t launch_one(FirArgs& a, hipStream_t s) {
-    constexpr bool AMAX = MODE == FIR_OUT_AMAX;
     constexpr int QM = mode_qm(MODE);
     const int ct = a.W / VEC;
     // Frames per thread (a multiple of MT).  Measured on MI355X: 2*MT (at
@@ -548,12 +544,12 @@ hipError_t launch_one(FirArgs& a, hipStream_t s) {
     // FP32 mode can turn them off for tuning sweeps.
     if constexpr (MODE == FIR_OUT_F32) {
         if (tune.nt == 0) {
-            hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, false, false, QM_NONE>), dim3((unsigned)blocks), dim3(256), 0, s,
+            hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, false, QM_NONE>), dim3((unsigned)blocks), dim3(256), 0, s,
                                a, TF);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, AMAX, true, QM>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
+    hipLaunchKernelGGL((fir_kernel<VEC, MT, EXACT, true, QM>), dim3((unsigned)blocks), dim3(256), 0, s, a, TF);
     return hipGetLastError();
 }
 
@@ -616,12 +612,11 @@ hipError_t launch_mode(FirArgs& a, int vec, hipStream_t s) {
 
 template <int MODE>
 hipError_t launch_batch_mode(const BatchTable* t, int max_m, bool all_exact, int grid, hipStream_t s) {
-    constexpr bool AMAX = MODE == FIR_OUT_AMAX;
     constexpr int QM = mode_qm(MODE);
     auto go = [&](auto mt_tag) -> hipError_t {
         constexpr int MT = decltype(mt_tag)::value;
-        if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, AMAX, QM>), dim3(grid), dim3(256), 0, s, t);
-        else hipLaunchKernelGGL((fir_batch_kernel<MT, false, AMAX, QM>), dim3(grid), dim3(256), 0, s, t);
+        if (all_exact) hipLaunchKernelGGL((fir_batch_kernel<MT, true, QM>), dim3(grid), dim3(256), 0, s, t);
+        else hipLaunchKernelGGL((fir_batch_kernel<MT, false, QM>), dim3(grid), dim3(256), 0, s, t);
         return hipGetLastError();
     };
     if (max_m <= 1) return go(std::integral_constant<int, 1>{});
