@@ -475,6 +475,15 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored",
+                    help="comma-separated precision forms of the form tables (form or form/factored)")
+    ap.add_argument("--form-workloads", default="real,wide",
+                    help="comma-separated workloads of the form tables: real (1024-channel real stream), "
+                         "wide (4096-channel complex 60 dB stream)")
+    ap.add_argument("--form-steps", type=int, default=0,
+                    help="timed steps per form (0: 20 on the real stream, 5 on the complex one)")
+    ap.add_argument("--no-fir-only", action="store_true", help="skip the FIR-only run")
+    ap.add_argument("--no-ops", action="store_true", help="skip the standalone building blocks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -542,12 +551,18 @@ def main():
     if not args.no_forms:
         from oracle import Oracle
         o = Oracle()
-        forms = ["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "fp8", "mxfp8", "fp32/factored"]
-        result["forms"] = {w.name: forms_table(w, forms, 20, 5, torch, o, 24)}
+        forms = [f for f in args.forms.split(",") if f]
+        fw = set(args.form_workloads.split(","))
+        fs = args.form_steps
+        result["forms"] = {}
+        if "real" in fw:
+            result["forms"][w.name] = forms_table(w, forms, fs or 20, min(5, fs or 5), torch, o, 24)
         del xd
-        wd = workloads.wide_dynamic_range()
-        result["forms"][wd.name] = forms_table(wd, forms, 5, 2, torch, o, 12)
-        del wd
+        if "wide" in fw:
+            wd = workloads.wide_dynamic_range()
+            result["forms"][wd.name] = forms_table(wd, forms, fs or 5, min(2, fs or 2), torch, o, 12)
+            del wd
+    if not args.no_forms and not args.no_fir_only:
         # FIR-only path on the real stream (the stage the FIR roofline measures).
         fplan = Plan(w.P, w.M, "r32", w.window, "fp32", "fir")
         xd = torch.from_numpy(w.x).cuda()
@@ -559,7 +574,7 @@ def main():
         del fout, xd
         fplan.close()
 
-    if not args.no_forms:
+    if not args.no_forms and not args.no_ops:
         result["ops"] = ops_bench(torch)
     if not args.no_batched:
         log("[bench] batched ragged workload")

@@ -26,6 +26,15 @@
  *     Device work is asynchronous on that stream unless stated otherwise.
  *   - Sizes are int64_t counts of samples or frames, never bytes, unless the
  *     name says _bytes.
+ *   - A plan (and a batch context) owns device scratch that every call of it
+ *     uses: the workspace between the FIR and the DFT, per-frame scales,
+ *     argument tables.  Calls of one plan on different streams are therefore
+ *     ordered by the library: a call on another stream than the previous
+ *     call's first waits (hipStreamWaitEvent) for that call's work.  Calls
+ *     captured into a graph are not ordered this way; the capturing caller
+ *     orders the graph's launches.  Plans, states and batch contexts are
+ *     thread-compatible, not thread-safe: one host thread calls an object at
+ *     a time.
  */
 #ifndef TINA_PFB_H
 #define TINA_PFB_H

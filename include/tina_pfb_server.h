@@ -78,7 +78,11 @@ tina_status tina_server_stream_create(tina_server_t server, int32_t channels, in
  * flags: TINA_REQ_DEVICE_BUFFERS -- host_in and host_out are device memory
  * on the server's device (the caller's; 4-byte aligned input, 8-byte aligned
  * output): the steps read and write them in place, no copy is made and the
- * arena (hbm_budget_bytes) is not used, so admission waits only for a slot. */
+ * arena (hbm_budget_bytes) is not used, so admission waits only for a slot.
+ * The input may still be being written when submit is called: submit records
+ * an event on ready_stream (a hipStream_t; NULL is the default stream), and
+ * the request joins no step before the work enqueued there so far is done.
+ * ready_stream is ignored for host buffers. */
 #define TINA_REQ_DEVICE_BUFFERS 1
 typedef struct tina_request {
     int32_t stream_id;
@@ -87,6 +91,7 @@ typedef struct tina_request {
     int64_t n_samples;
     void* host_out;
     int64_t out_capacity_frames;
+    void* ready_stream;        /* TINA_REQ_DEVICE_BUFFERS: stream that writes host_in */
 } tina_request;
 
 typedef struct tina_result {

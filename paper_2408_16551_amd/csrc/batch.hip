@@ -94,8 +94,10 @@ struct tina_pfb_batch_s {
     // the kernel variant: tap ring, exact taps, launch shape.
     std::map<std::string, hipGraphExec_t> graphs;
     int64_t graph_gemm_grid = 0;  // fixed GEMM grid of captured steps (0: no graphs)
+    StreamOrder order;            // every call shares ws, amax, fexp and d_table
 
     void release() {
+        order.release();
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
         if (table_free) (void)hipEventDestroy(table_free);
@@ -363,6 +365,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
                       const std::vector<int64_t>& frames, bool use_graph = false) {
     const std::vector<GroupPlan> groups = make_groups(b, w, frames, n);
     use_graph = use_graph && groups.size() == 1;
+    HIP_TRY(b->order.begin(s));
     for (const GroupPlan& g : groups) {
         if (b->table_pending) {
             HIP_TRY(hipEventSynchronize(b->table_free));  // host copy of the table is free again
@@ -398,6 +401,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
             }
         }
     }
+    HIP_TRY(b->order.end(s));
     return TINA_OK;
 }
 

@@ -220,6 +220,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute: hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(p->order.begin(s));
 
     FirArgs fa{};
     fa.prefix = st ? st->buf[st->cur] : nullptr;
@@ -335,6 +336,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
         st->cur ^= 1;
         st->residue = r2;
     }
+    HIP_TRY(p->order.end(s));
     if (frames_written) *frames_written = F;
     return TINA_OK;
 }
@@ -382,6 +384,7 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t p, const void* d_X, int64_t F, v
     DeviceScope ds(p->device);
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "synthesize: hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(p->order.begin(s));
     const int64_t hist_floats = (int64_t)(p->M - 1) * p->W;
     const float* prefix = st ? st->buf[st->cur] : nullptr;
     int scratch = 0;
@@ -424,6 +427,7 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t p, const void* d_X, int64_t F, v
         scratch ^= 1;
     }
     if (st && F > 0) st->cur ^= 1;
+    HIP_TRY(p->order.end(s));
     if (written) *written = F * p->P;
     return TINA_OK;
 }

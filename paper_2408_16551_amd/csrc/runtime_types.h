@@ -31,6 +31,44 @@ struct DeviceScope {
     }
 };
 
+// Orders the calls of one object (a plan, a batch) whose device scratch --
+// workspace, argument tables -- every call shares: a call enqueued on another
+// stream than the previous call's first waits for that call's work.  Calls
+// under stream capture are left to the capturing caller to order.
+struct StreamOrder {
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;
+    bool valid = false;
+
+    static bool capturing(hipStream_t s) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    }
+    hipError_t begin(hipStream_t s) const {
+        if (!valid || last == s || capturing(s)) return hipSuccess;
+        return hipStreamWaitEvent(s, ev, 0);
+    }
+    hipError_t end(hipStream_t s) {
+        if (capturing(s)) {
+            valid = false;
+            return hipSuccess;
+        }
+        if (!ev) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipEventRecord(ev, s);
+        valid = e == hipSuccess;
+        last = s;
+        return e;
+    }
+    void release() {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+        valid = false;
+    }
+};
+
 constexpr int64_t kWorkspaceBytes = 512ll << 20;  // FP32 FIR output per piece
 
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -56,6 +94,7 @@ struct tina_pfb_plan_s {
     int32_t* fexp = nullptr;    // per-frame scale exponents of a workspace piece (per-frame scaled forms)
     int64_t ch_frames = 0;
     int64_t amax_parts_cap = 0;
+    StreamOrder order;          // execute/synthesize calls share ws, amax, fexp and hist
     // Stage timing (tina_pfb_profile_*): recorded event pairs per stage.
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -77,6 +116,7 @@ struct tina_pfb_plan_s {
     }
 
     void release() {
+        order.release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         clear_events();

@@ -200,8 +200,6 @@ void tina_server_s::loop() {
                     }
                     q->off_in = oi;
                     q->off_out = oo;
-                } else {
-                    q->in_ready = true;  // already on the device
                 }
                 q->phase = ACTIVE;
                 q->res.t_admit_us = now_us();
@@ -216,7 +214,7 @@ void tina_server_s::loop() {
             stats.arena_high_water = arena.high();
         }
         for (Req* q : admitted) {  // input copies, outside the lock
-            if (q->r.flags & TINA_REQ_DEVICE_BUFFERS) continue;
+            if (q->r.flags & TINA_REQ_DEVICE_BUFFERS) continue;  // ev_in was recorded at submit
             if (q->in_bytes > 0 && q->r.n_samples > 0)
                 (void)hipMemcpyAsync(arena_base + q->off_in, q->r.host_in, q->r.n_samples * q->sample_bytes,
                                      hipMemcpyHostToDevice, s_h2d);
@@ -481,6 +479,10 @@ tina_status tina_pfb_submit(tina_server_t sv, const tina_request* r, uint64_t* i
         hipEventCreateWithFlags(&q->ev_out, hipEventDisableTiming) != hipSuccess) {
         destroy_req(q);
         return fail(TINA_ERR_DEVICE, "submit: events");
+    }
+    if (dev && hipEventRecord(q->ev_in, (hipStream_t)r->ready_stream) != hipSuccess) {
+        destroy_req(q);
+        return fail(TINA_ERR_DEVICE, "submit: recording the input-ready event on ready_stream");
     }
     q->id = sv->next_id++;
     q->res.t_submit_us = t;

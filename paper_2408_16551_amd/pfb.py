@@ -60,7 +60,7 @@ class _ServerConfig(ctypes.Structure):
 class _Request(ctypes.Structure):
     _fields_ = [("stream_id", ctypes.c_int32), ("flags", ctypes.c_int32), ("host_in", ctypes.c_void_p),
                 ("n_samples", ctypes.c_int64), ("host_out", ctypes.c_void_p),
-                ("out_capacity_frames", ctypes.c_int64)]
+                ("out_capacity_frames", ctypes.c_int64), ("ready_stream", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):
@@ -155,6 +155,41 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def check_device_tensor(t, what: str, dtype, ndim: int, device: int, cols=None):
+    """Raise ValueError unless t is a contiguous torch tensor of `dtype` with
+    `ndim` dimensions (and `cols` columns) on cuda:`device`: the C ABI takes
+    raw pointers, so a wrong type or layout would be read or written out of
+    bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise ValueError(f"{what} must have {ndim} dimension(s), got shape {tuple(t.shape)}")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{what} must have {cols} columns, got shape {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{what} must be on cuda:{device}, got {t.device}")
+
+
+def check_host_array(a, what: str, dtype, ndim: int, cols=None):
+    """Raise ValueError unless a is a C-contiguous numpy array of `dtype` with
+    `ndim` dimensions (and `cols` columns)."""
+    if not isinstance(a, np.ndarray):
+        raise ValueError(f"{what} must be a numpy array or a CUDA tensor, got {type(a).__name__}")
+    if a.dtype != np.dtype(dtype):
+        raise ValueError(f"{what} must be {np.dtype(dtype)}, got {a.dtype}")
+    if a.ndim != ndim:
+        raise ValueError(f"{what} must have {ndim} dimension(s), got shape {a.shape}")
+    if cols is not None and a.shape[1] != cols:
+        raise ValueError(f"{what} must have {cols} columns, got shape {a.shape}")
+    if not a.flags.c_contiguous:
+        raise ValueError(f"{what} must be C-contiguous")
+
+
 class Plan:
     """A filter-bank plan: P channels, M taps per branch, a prototype window,
     the sample type, the DFT precision form and the output kind."""
@@ -235,13 +270,14 @@ class Plan:
         output tensor (frames x channels_out)."""
         import torch
         want = torch.complex64 if self.complex_input else torch.float32
-        if x.dtype != want or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
-            raise ValueError(f"input must be a contiguous 1-D {want} CUDA tensor")
+        check_device_tensor(x, "input", want, 1, self.device)
         n = x.numel()
         frames = self.output_frames(n, state)
         if out is None:
             out = self.alloc_out(frames)
-        cap = out.shape[0] if out.dim() == 2 and out.shape[1] == self.channels_out else 0
+        out_dt = want if self.output == "fir" else torch.complex64
+        check_device_tensor(out, "out", out_dt, 2, self.device, cols=self.channels_out)
+        cap = out.shape[0]
         fw = ctypes.c_int64()
         check(load().tina_pfb_execute(self.handle, ctypes.c_void_p(x.data_ptr() if n else 0), n,
                                       ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap,
@@ -254,11 +290,11 @@ class Plan:
         """Synthesis bank of an output="inverse" plan: X (frames x P complex64
         device tensor) -> frames * P complex64 samples."""
         import torch
-        if X.dtype != torch.complex64 or X.dim() != 2 or X.shape[1] != self.P or not X.is_cuda or not X.is_contiguous():
-            raise ValueError("X must be a contiguous frames x P complex64 CUDA tensor")
+        check_device_tensor(X, "X", torch.complex64, 2, self.device, cols=self.P)
         F = X.shape[0]
         if out is None:
             out = torch.empty(F * self.P, dtype=torch.complex64, device=X.device)
+        check_device_tensor(out, "out", torch.complex64, 1, self.device)
         n = ctypes.c_int64()
         check(load().tina_pfb_synthesize(self.handle, ctypes.c_void_p(X.data_ptr() if F else 0), F,
                                          ctypes.c_void_p(out.data_ptr() if out.numel() else 0), out.numel(),
@@ -333,10 +369,14 @@ class Batch:
 
     @staticmethod
     def _works(items):
+        import torch
         arr = (_Work * max(1, len(items)))()
         for i, it in enumerate(items):
             plan, x, out = it[0], it[1], it[2]
             state = it[3] if len(it) > 3 else None
+            want = torch.complex64 if plan.complex_input else torch.float32
+            check_device_tensor(x, f"item {i} input", want, 1, plan.device)
+            check_device_tensor(out, f"item {i} out", torch.complex64, 2, plan.device, cols=plan.channels_out)
             w = arr[i]
             w.plan = plan.handle.value
             w.state = state.handle.value if state is not None else None
@@ -398,6 +438,7 @@ class Server:
         h = ctypes.c_void_p()
         check(load().tina_server_create(ctypes.byref(c), ctypes.byref(h)))
         self.handle = h
+        self.device = int(device)
         self._streams = {}
         self._lent = {}   # request id -> (input, output) kept alive until done
 
@@ -429,20 +470,28 @@ class Server:
         out (complex64, frames x channels).  Host numpy arrays are copied in and
         out by the server; CUDA tensors (both) are used in place on the device
         (TINA_REQ_DEVICE_BUFFERS).  Both are held until the request is collected."""
+        if sid not in self._streams:
+            raise ValueError(f"unknown stream id {sid}")
+        P, st = self._streams[sid]
         r = _Request()
         r.stream_id = int(sid)
         if hasattr(x, "is_cuda"):
-            if not (x.is_cuda and getattr(out, "is_cuda", False) and x.is_contiguous() and out.is_contiguous()):
-                raise ValueError("device requests need contiguous CUDA tensors for input and output")
+            import torch
+            check_device_tensor(x, "input", torch.complex64 if st == "c64" else torch.float32, 1, self.device)
+            check_device_tensor(out, "out", torch.complex64, 2, self.device, cols=self.out_rows(sid))
             r.flags = 1
             r.host_in = x.data_ptr() if x.numel() else None
             r.n_samples = x.numel()
             r.host_out = out.data_ptr() if out.numel() else None
+            # the server waits for the work enqueued so far on the current stream (it may write x)
+            r.ready_stream = torch.cuda.current_stream(self.device).cuda_stream
         else:
+            check_host_array(x, "input", np.complex64 if st == "c64" else np.float32, 1)
+            check_host_array(out, "out", np.complex64, 2, cols=self.out_rows(sid))
             r.host_in = x.ctypes.data if x.size else None
             r.n_samples = x.size
             r.host_out = out.ctypes.data if out.size else None
-        r.out_capacity_frames = out.shape[0] if out.ndim == 2 else 0
+        r.out_capacity_frames = out.shape[0]
         rid = ctypes.c_uint64()
         check(load().tina_pfb_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
         self._lent[rid.value] = (x, out)
@@ -486,12 +535,14 @@ def unfold(x, width: int, stride: int = 1, out=None, stream=None):
     """Sliding-window unfold Y[i][j] = x[i*stride + j] of a 1-D float32 device
     tensor; returns the rows x width tensor."""
     import torch
-    if x.dtype != torch.float32 or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
-        raise ValueError("x must be a contiguous 1-D float32 CUDA tensor")
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA tensor")
+    check_device_tensor(x, "x", torch.float32, 1, x.device.index)
     n = x.numel()
     rows = 0 if n < width else (n - width) // stride + 1
     if out is None:
         out = torch.empty((rows, width), dtype=torch.float32, device=x.device)
+    check_device_tensor(out, "out", torch.float32, 2, x.device.index, cols=int(width))
     got = ctypes.c_int64()
     check(load().tina_unfold(ctypes.c_void_p(x.data_ptr() if n else 0), n, int(width), int(stride),
                              ctypes.c_void_p(out.data_ptr() if out.numel() else 0), out.shape[0] if out.dim() == 2 else 0,
@@ -508,6 +559,7 @@ class Fir:
         check(load().tina_fir_create(int(device), a.ctypes.data_as(ctypes.c_void_p), a.size, SAMPLE[sample_type],
                                      ctypes.byref(h)))
         self.handle = h
+        self.device = int(device)
         self.complex_input = sample_type == "c64"
 
     def close(self):
@@ -524,10 +576,12 @@ class Fir:
     def __call__(self, x, out=None, stream=None):
         import torch
         want = torch.complex64 if self.complex_input else torch.float32
-        if x.dtype != want or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
-            raise ValueError(f"x must be a contiguous 1-D {want} CUDA tensor")
+        check_device_tensor(x, "x", want, 1, self.device)
         if out is None:
             out = torch.empty_like(x)
+        check_device_tensor(out, "out", want, 1, self.device)
+        if out.numel() < x.numel():
+            raise ValueError(f"out holds {out.numel()} samples, fewer than the input's {x.numel()}")
         check(load().tina_fir_execute(self.handle, ctypes.c_void_p(x.data_ptr() if x.numel() else 0), x.numel(),
                                       ctypes.c_void_p(out.data_ptr() if out.numel() else 0), _stream_handle(stream)))
         return out

@@ -147,3 +147,34 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=300)
     assert r.returncode != 0
     assert "--gpus must be 1" in (r.stdout + r.stderr)
+
+
+def test_binding_validates_buffers_before_the_abi():
+    # The C ABI takes raw pointers: the binding must refuse a buffer of the
+    # wrong type, shape, layout or device before any call is made.
+    import numpy as np
+    import torch
+    from paper_2408_16551_amd.pfb import check_device_tensor, check_host_array
+    f32 = torch.zeros(8, 9, dtype=torch.float32)
+    c64 = torch.zeros(8, 9, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="complex64"):
+        check_device_tensor(f32, "out", torch.complex64, 2, 0, cols=9)      # float32 out: half the bytes
+    with pytest.raises(ValueError, match="dimension"):
+        check_device_tensor(c64.reshape(-1), "out", torch.complex64, 2, 0, cols=9)
+    with pytest.raises(ValueError, match="columns"):
+        check_device_tensor(c64, "out", torch.complex64, 2, 0, cols=10)
+    with pytest.raises(ValueError, match="contiguous"):
+        check_device_tensor(c64.t(), "out", torch.complex64, 2, 0, cols=8)
+    with pytest.raises(ValueError, match="cuda:0"):
+        check_device_tensor(c64, "out", torch.complex64, 2, 0, cols=9)      # a CPU tensor
+    with pytest.raises(ValueError, match="torch tensor"):
+        check_device_tensor(np.zeros((8, 9), np.complex64), "out", torch.complex64, 2, 0)
+    check_host_array(np.zeros((8, 9), np.complex64), "out", np.complex64, 2, cols=9)
+    with pytest.raises(ValueError, match="complex64"):
+        check_host_array(np.zeros((8, 9), np.float32), "out", np.complex64, 2, cols=9)
+    with pytest.raises(ValueError, match="float32"):
+        check_host_array(np.zeros(16, np.complex64), "input", np.float32, 1)   # complex input on a real stream
+    with pytest.raises(ValueError, match="C-contiguous"):
+        check_host_array(np.zeros((9, 8), np.complex64).T, "out", np.complex64, 2, cols=9)
+    with pytest.raises(ValueError, match="columns"):
+        check_host_array(np.zeros((8, 5), np.complex64), "out", np.complex64, 2, cols=9)
