@@ -219,6 +219,33 @@ tina_status tina_pfb_execute(tina_pfb_plan_t plan, const void* d_in, int64_t n_s
                              tina_pfb_state_t state, int64_t* frames_written, void* stream);
 
 /*
+ * Allocation-free execute, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, validation and results as tina_pfb_execute
+ * (the same kernels run: outputs are bit for bit those of tina_pfb_execute),
+ * but the FIR output / operand codes and the per-frame scales live in a
+ * static 64 MiB device array of the library instead of the plan's workspace,
+ * so the plan may be created with workspace_bytes < 0.  The call makes no
+ * hipMalloc, hipFree or other allocating call; the array's device address is
+ * looked up once per device on the first call there.
+ * Limit: one call handles at most floor((64 MiB - s) / bytes_per_frame)
+ * frames, rounded down to a multiple of 128 when at least 128, where W is the
+ * floats per frame (P for R32, 2P for C64), bytes_per_frame = 4 W, and for
+ * the per-frame scaled forms (FP16, FP16X3, FP8_FRAME) bytes_per_frame =
+ * 4 W + 4 max(1, W/32) + 4 and s = 512 (else s = 0): 16384 frames for
+ * P = 1024 real FP32.  More frames return TINA_ERR_TOO_LARGE before anything
+ * is enqueued.  FIR-only plans use no scratch and have no limit.
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (on different streams, or from different threads) race
+ * and corrupt each other's output.  Calls are not ordered against the plan's
+ * tina_pfb_execute calls (they do not share memory), and are never timed by
+ * tina_pfb_profile_*.
+ */
+tina_status tina_pfb_execute_noalloc(tina_pfb_plan_t plan, const void* d_in, int64_t n_samples,
+                                     void* d_out, int64_t out_capacity_frames,
+                                     tina_pfb_state_t state, int64_t* frames_written, void* stream);
+
+/*
  * Synthesis (inverse) filter bank of a TINA_OUT_INVERSE plan: for n_frames
  * frames of P complex64 channel values at d_X (device, row-major, 16-byte
  * aligned), the

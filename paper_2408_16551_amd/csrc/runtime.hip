@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -199,28 +200,51 @@ tina_status tina_pfb_output_frames(tina_pfb_plan_t p, tina_pfb_state_t st, int64
     return TINA_OK;
 }
 
-tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, void* d_out, int64_t cap,
-                             tina_pfb_state_t st, int64_t* frames_written, void* stream) {
-    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL plan");
-    if (n < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: negative sample count");
-    if (n > 0 && !d_in) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL input");
-    if (st && st->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: state belongs to another plan");
+}  // extern "C"
+
+namespace {
+
+// Device memory one execute call works in between the FIR and the DFT: the
+// FIR output (or the GEMM operand codes), per-frame partial maxima and frame
+// exponents, sized for pieces of ch_frames frames.
+struct ExecWorkspace {
+    float* ws = nullptr;
+    float* amax = nullptr;
+    int32_t* fexp = nullptr;
+    int64_t ch_frames = 0;
+    bool use_plan = true;  // the plan's own workspace: calls are ordered across streams and may be timed
+};
+
+tina_status execute_with(tina_pfb_plan_s* p, const void* d_in, int64_t n, void* d_out, int64_t cap,
+                         tina_pfb_state_t st, int64_t* frames_written, void* stream, const ExecWorkspace& w,
+                         const char* who) {
+    const std::string name(who);
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": NULL plan");
+    if (n < 0) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": negative sample count");
+    if (n > 0 && !d_in) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": NULL input");
+    if (st && st->plan != p) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": state belongs to another plan");
     const size_t sbytes = p->cf * sizeof(float);
-    if ((uintptr_t)d_in % sbytes) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: input not aligned to its sample size");
+    if ((uintptr_t)d_in % sbytes) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": input not aligned to its sample size");
     const int64_t r = st ? st->residue : 0;
     const int64_t F = (r + n) / p->P;
-    if (F > 0 && !d_out) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL output");
+    if (F > 0 && !d_out) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": NULL output");
     const size_t obytes = p->output == TINA_OUT_PFB ? 8 : sbytes;
-    if ((uintptr_t)d_out % obytes) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output misaligned");
-    if (F > cap) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: output capacity (" + std::to_string(cap) +
+    if ((uintptr_t)d_out % obytes) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": output misaligned");
+    if (F > cap) return fail(TINA_ERR_INVALID_ARGUMENT, name + ": output capacity (" + std::to_string(cap) +
                                                          " frames) below frame count " + std::to_string(F));
-    if (p->output == TINA_OUT_PFB && p->ch_frames == 0)
-        return fail(TINA_ERR_UNSUPPORTED, "execute: plan was created without a workspace (batch/server use only)");
-    if (p->output == TINA_OUT_INVERSE) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: synthesis plans run through tina_pfb_synthesize");
+    if (p->output == TINA_OUT_INVERSE)
+        return fail(TINA_ERR_INVALID_ARGUMENT, name + ": synthesis plans run through tina_pfb_synthesize");
+    if (p->output == TINA_OUT_PFB && w.ch_frames == 0)
+        return fail(TINA_ERR_UNSUPPORTED, name + ": plan was created without a workspace (batch/server use only)");
+    if (!w.use_plan && p->output == TINA_OUT_PFB && F > w.ch_frames)
+        return fail(TINA_ERR_TOO_LARGE, name + ": " + std::to_string(F) + " frames exceed the " +
+                                            std::to_string(w.ch_frames) + " frames per call that the " +
+                                            std::to_string(kStaticScratchBytes >> 20) +
+                                            " MiB static scratch holds for this plan");
     DeviceScope ds(p->device);
-    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute: hipSetDevice failed");
+    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, name + ": hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(p->order.begin(s));
+    if (w.use_plan) HIP_TRY(p->order.begin(s));
 
     FirArgs fa{};
     fa.prefix = st ? st->buf[st->cur] : nullptr;
@@ -236,7 +260,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     // Records a HIP event pair around one stage launch when profiling.
     auto timed = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& list, auto&& launch) -> hipError_t {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (p->profiling) {
+        if (p->profiling && w.use_plan) {
             e0 = p->next_event();
             e1 = p->next_event();
             if (e0 && e1) (void)hipEventRecord(e0, s);
@@ -259,13 +283,13 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
     } else {
         const int form = p->precision;
         const int64_t ldo = p->cf == 2 ? 2 * (int64_t)p->P : (int64_t)p->P + 2;
-        for (int64_t c0 = 0; c0 < F; c0 += p->ch_frames) {
-            const int64_t Fc = F - c0 < p->ch_frames ? F - c0 : p->ch_frames;
-            fa.y = p->ws;
+        for (int64_t c0 = 0; c0 < F; c0 += w.ch_frames) {
+            const int64_t Fc = F - c0 < w.ch_frames ? F - c0 : w.ch_frames;
+            fa.y = w.ws;
             fa.ldy = p->W;
             fa.g0 = c0;
             fa.F = Fc;
-            fa.amax = form_scaled(form) ? p->amax : nullptr;
+            fa.amax = form_scaled(form) ? w.amax : nullptr;
             // Operand-form FIR output in the FP32 workspace (4 bytes per float):
             // E4M3 codes (then the block scales), or the 16-bit piece(s) one
             // after the other; per-frame scaled forms also keep the frames'
@@ -273,12 +297,12 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             fa.qmode = form_fir_qmode(form);
             if (fa.qmode != 0) {
                 fa.y = nullptr;
-                fa.q = (uint8_t*)p->ws;
+                fa.q = (uint8_t*)w.ws;
                 fa.ldq = p->W;
-                if (form_mx(form)) fa.qs = (uint8_t*)p->ws + mx_codes_bytes(p->ch_frames, p->W);
+                if (form_mx(form)) fa.qs = (uint8_t*)w.ws + mx_codes_bytes(w.ch_frames, p->W);
                 if (form == TINA_PREC_BF16X3 || form == TINA_PREC_FP16X3)
-                    fa.q1 = (uint8_t*)p->ws + (int64_t)p->ch_frames * p->W * 2;
-                if (form_scaled(form)) fa.fexp = p->fexp;
+                    fa.q1 = (uint8_t*)w.ws + (int64_t)w.ch_frames * p->W * 2;
+                if (form_scaled(form)) fa.fexp = w.fexp;
             }
             if (p->dft_algorithm == TINA_DFT_FUSED && fused_supported(fa, form)) {
                 GemmArgs ga{};
@@ -296,7 +320,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
             HIP_TRY(timed(p->ev_fir, [&] { return launch_fir(fa, s); }));
             if (p->dft_algorithm == TINA_DFT_FACTORED) {
                 FftArgs xa{};
-                xa.y = p->ws;
+                xa.y = w.ws;
                 xa.ldy = p->W;
                 xa.F = Fc;
                 xa.mat1 = p->fft_mat1;
@@ -311,7 +335,7 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
                 continue;
             }
             GemmArgs ga{};
-            ga.A = p->ws;
+            ga.A = w.ws;
             ga.lda = p->W;
             ga.B0 = p->B[0];
             ga.B1 = p->B[1];
@@ -336,9 +360,86 @@ tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, voi
         st->cur ^= 1;
         st->residue = r2;
     }
-    HIP_TRY(p->order.end(s));
+    if (w.use_plan) HIP_TRY(p->order.end(s));
     if (frames_written) *frames_written = F;
     return TINA_OK;
+}
+
+// Static scratch of the allocation-free execute: one per device, at a
+// device address that hipGetSymbolAddress reports once per device (the host
+// name of the array is not a device address).
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The scratch's device address on the current device `dev` (set up on the
+// first call there); nullptr with the HIP error in *e on failure.
+void* scratch_address(int dev, hipError_t* e) {
+    *e = hipSuccess;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *e = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        *e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*e != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+// Frames per call that the scratch holds for plan p, and the workspace laid
+// out in it at base (FIR output or operand codes, then per-frame partial
+// maxima and exponents, each 256-byte aligned).
+ExecWorkspace scratch_workspace(const tina_pfb_plan_s* p, uint8_t* base) {
+    ExecWorkspace w;
+    w.use_plan = false;
+    const bool scaled = form_scaled(p->precision) && p->output == TINA_OUT_PFB;
+    const int64_t parts = p->W / 32 > 1 ? p->W / 32 : 1;  // the most partial maxima per frame (as at plan time)
+    const int64_t per_frame = (int64_t)p->W * 4 + (scaled ? parts * 4 + 4 : 0);
+    int64_t ch = (kStaticScratchBytes - (scaled ? 512 : 0)) / per_frame;  // 512: alignment of maxima, exponents
+    if (ch >= 128) ch = ch / 128 * 128;
+    w.ch_frames = ch;
+    w.ws = (float*)base;
+    if (scaled) {
+        const int64_t amax_off = align256(ch * p->W * 4);
+        const int64_t fexp_off = align256(amax_off + ch * parts * 4);
+        w.amax = (float*)(base + amax_off);
+        w.fexp = (int32_t*)(base + fexp_off);
+    }
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+tina_status tina_pfb_execute(tina_pfb_plan_t p, const void* d_in, int64_t n, void* d_out, int64_t cap,
+                             tina_pfb_state_t st, int64_t* frames_written, void* stream) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute: NULL plan");
+    ExecWorkspace w;
+    w.ws = p->ws;
+    w.amax = p->amax;
+    w.fexp = p->fexp;
+    w.ch_frames = p->ch_frames;
+    return execute_with(p, d_in, n, d_out, cap, st, frames_written, stream, w, "execute");
+}
+
+tina_status tina_pfb_execute_noalloc(tina_pfb_plan_t p, const void* d_in, int64_t n, void* d_out, int64_t cap,
+                                     tina_pfb_state_t st, int64_t* frames_written, void* stream) {
+    if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "execute_noalloc: NULL plan");
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "execute_noalloc: hipSetDevice failed");
+    hipError_t e;
+    void* base = scratch_address(p->device, &e);
+    if (!base) return fail(TINA_ERR_DEVICE, std::string("execute_noalloc: scratch address: ") + hipGetErrorString(e));
+    return execute_with(p, d_in, n, d_out, cap, st, frames_written, stream,
+                        scratch_workspace(p, (uint8_t*)base), "execute_noalloc");
 }
 
 tina_status tina_pfb_profile_enable(tina_pfb_plan_t p, int enable) {

@@ -70,6 +70,7 @@ struct StreamOrder {
 };
 
 constexpr int64_t kWorkspaceBytes = 512ll << 20;  // FP32 FIR output per piece
+constexpr int64_t kStaticScratchBytes = 64ll << 20;  // static scratch of tina_pfb_execute_noalloc, per device
 
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 

@@ -26,7 +26,7 @@ STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 
 EXPORTS = [
     "tina_last_error", "tina_version",
     "tina_pfb_plan", "tina_pfb_plan_destroy", "tina_pfb_channels_out", "tina_pfb_plan_taps",
-    "tina_pfb_output_frames", "tina_pfb_execute", "tina_pfb_synthesize",
+    "tina_pfb_output_frames", "tina_pfb_execute", "tina_pfb_execute_noalloc", "tina_pfb_synthesize",
     "tina_pfb_state_create", "tina_pfb_state_destroy", "tina_pfb_state_reset", "tina_pfb_state_size",
     "tina_pfb_state_export", "tina_pfb_state_import",
     "tina_pfb_profile_enable", "tina_pfb_profile_read",
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
         "tina_pfb_plan_taps": ([vp, vp], i32),
         "tina_pfb_output_frames": ([vp, vp, i64, P64], i32),
         "tina_pfb_execute": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
+        "tina_pfb_execute_noalloc": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
         "tina_pfb_synthesize": ([vp, vp, i64, vp, i64, vp, P64, vp], i32),
         "tina_pfb_state_create": ([vp, ctypes.POINTER(vp)], i32),
         "tina_pfb_state_destroy": ([vp], i32),
@@ -265,9 +266,11 @@ class Plan:
             dt = torch.complex64
         return torch.empty((frames, self.channels_out), dtype=dt, device=f"cuda:{self.device}")
 
-    def execute(self, x, out=None, state: "State | None" = None, stream=None):
+    def execute(self, x, out=None, state: "State | None" = None, stream=None, noalloc: bool = False):
         """Run on a 1-D device tensor x (float32 or complex64); returns the
-        output tensor (frames x channels_out)."""
+        output tensor (frames x channels_out).  noalloc=True calls
+        tina_pfb_execute_noalloc (the library's static scratch instead of the
+        plan's workspace; pass `out` too so nothing is allocated here)."""
         import torch
         want = torch.complex64 if self.complex_input else torch.float32
         check_device_tensor(x, "input", want, 1, self.device)
@@ -279,7 +282,8 @@ class Plan:
         check_device_tensor(out, "out", out_dt, 2, self.device, cols=self.channels_out)
         cap = out.shape[0]
         fw = ctypes.c_int64()
-        check(load().tina_pfb_execute(self.handle, ctypes.c_void_p(x.data_ptr() if n else 0), n,
+        fn = load().tina_pfb_execute_noalloc if noalloc else load().tina_pfb_execute
+        check(fn(self.handle, ctypes.c_void_p(x.data_ptr() if n else 0), n,
                                       ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap,
                                       state.handle if state else None, ctypes.byref(fw), _stream_handle(stream)))
         return out[: fw.value]
