@@ -62,15 +62,15 @@ __device__ inline float f16_round(float a) { return (float)(_Float16)a; }
 // af[bm][piece][read], bf[bn][piece][read]: the lane's 16-byte K slices.
 // sa/sb (block-scaled form): the lane's E8M0 scale in the low byte, one per
 // 32-K block of the lane's row / column.
-template <int FORM, int NP, int RD, int WN>
-__device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[WN][NP][RD],
-                                          f32x16 (&acc)[2][WN], f32x16 (&acc2)[2][WN], const int (&sa)[2],
-                                          const int (&sb)[WN]) {
+template <int FORM, int NP, int RD, int TM, int WN>
+__device__ __forceinline__ void mfma_block(const uint4 (&af)[TM][NP][RD], const uint4 (&bf)[WN][NP][RD],
+                                           f32x16 (&acc)[TM][WN], f32x16 (&acc2)[TM][WN], const int (&sa)[TM],
+                                           const int (&sb)[WN]) {
     if constexpr (FORM == FORM_FP32) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
+            for (int bm = 0; bm < TM; ++bm)
 #pragma unroll
                 for (int bn = 0; bn < WN; ++bn) {
                     const f32x4 av = __builtin_bit_cast(f32x4, af[bm][0][0]);
@@ -84,7 +84,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 #pragma unroll
         for (int term = 0; term < NT; ++term)
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
+            for (int bm = 0; bm < TM; ++bm)
 #pragma unroll
                 for (int bn = 0; bn < WN; ++bn) {
                     const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
 #pragma unroll
         for (int term = 0; term < NT; ++term)
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
+            for (int bm = 0; bm < TM; ++bm)
 #pragma unroll
                 for (int bn = 0; bn < WN; ++bn) {
                     const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
                 }
     } else {
 #pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
+        for (int bm = 0; bm < TM; ++bm)
 #pragma unroll
             for (int bn = 0; bn < WN; ++bn) {
                 i32x8 av, bv;
@@ -129,6 +129,13 @@ __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const ui
                                                                                   0x7f7f7f7f, 0, 0x7f7f7f7f);
             }
     }
+}
+
+template <int FORM, int NP, int RD, int WN>
+__device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[WN][NP][RD],
+                                          f32x16 (&acc)[2][WN], f32x16 (&acc2)[2][WN], const int (&sa)[2],
+                                          const int (&sb)[WN]) {
+    mfma_block<FORM, NP, RD, 2, WN>(af, bf, acc, acc2, sa, sb);
 }
 
 template <int FORM, int WN>
@@ -655,6 +662,380 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
     gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, ft::SCALED ? sm.fsc : nullptr);
 }
 
+// ------------------------------------------------------------- wide tiles
+// Raw-operand tile for the single-stream path: 8 waves (512 threads) in a
+// WGM x WGN grid, each wave TM x TN MFMA 32 x 32 blocks, so that each 16-byte
+// LDS read feeds more MFMA cycles and each byte fetched from L2 feeds more
+// products than in the 128 x 128 tile (whose two 64 x 64-wave blocks per CU
+// need as many LDS bytes per cycle as the LDS delivers).  One block per CU:
+// two LDS stages of K tiles (one barrier per K tile), the next tile's global
+// loads in flight in registers during a whole K tile of products.
+// ROWB: bytes of an operand row per K tile and piece.  The FP8 forms take one
+// 64-K slab per K tile: with two, the compiler keeps both slabs' 32-byte
+// fragments live across the next tile's LDS stores and runs out of registers.
+template <int FORM> struct WideCfg {  // 256 x 256 tiles, waves of 128 x 64
+    static constexpr int WGM = 2, WGN = 4, TM = 4, TN = 2;
+    static constexpr int ROWB = FT<FORM>::EB == 1 ? 64 : 128 / FT<FORM>::NP;
+};
+template <> struct WideCfg<FORM_FP16X3> {  // two accumulators: 128 x 256 tiles, waves of 64 x 64
+    static constexpr int WGM = 2, WGN = 4, TM = 2, TN = 2, ROWB = 64;
+};
+
+template <int FORM>
+struct WideGeom {
+    using cfg = WideCfg<FORM>;
+    static constexpr int WGM = cfg::WGM, WGN = cfg::WGN, TM = cfg::TM, TN = cfg::TN;
+    static constexpr int NP = FT<FORM>::NP, EB = FT<FORM>::EB, SLAB = FT<FORM>::SLAB, RD = SLAB / 32;
+    static constexpr int NTH = 64 * WGM * WGN;
+    static constexpr int BM = 32 * WGM * TM, BN = 32 * WGN * TN;
+    static constexpr int ROWB = cfg::ROWB;
+    static constexpr int RS = ROWB + 16;    // LDS row stride: 16 rows of 16-byte reads hit distinct banks
+    static constexpr int CPR = ROWB / 16;   // 16-byte chunks per row
+    static constexpr int STAGE = NP * (BM + BN) * RS;
+    static constexpr int QCH = BM * CPR / NTH, BCH = BN * CPR / NTH;  // chunks per thread per piece
+    static constexpr int BK = ROWB / EB;    // K elements per tile
+    static constexpr int NSLAB = ROWB / SLAB;
+    static_assert(BM * CPR % NTH == 0 && BN * CPR % NTH == 0, "whole chunks per thread");
+    static constexpr int SCW = (BM + BN + NTH - 1) / NTH;  // scale words per thread (block-scaled form)
+    static_assert(NSLAB >= 1, "a K tile holds whole MFMA slabs");
+};
+
+// Scale words (block-scaled form) and frame scales (per-frame scaled forms)
+// as empty bases when unused, so the bf16 hi + lo form's two stages fill the
+// 160 KiB of LDS exactly.
+template <int N, bool ON> struct WideMx { uint32_t mxs[2][N]; };
+template <int N> struct WideMx<N, false> {};
+template <int N, bool ON> struct WideFsc { float fsc[N]; };
+template <int N> struct WideFsc<N, false> {};
+
+template <int FORM>
+struct WideSmem : WideMx<WideGeom<FORM>::BM + WideGeom<FORM>::BN, FT<FORM>::MX>,
+                  WideFsc<WideGeom<FORM>::BM, FT<FORM>::SCALED> {
+    uint8_t tiles[2][WideGeom<FORM>::STAGE];
+};
+
+constexpr int WIDE_GROUP_M = 8;  // m-tiles swept per column of n-tiles (a CU-round of an XCD is ~ 8 x 4 tiles)
+
+template <int FORM>
+__device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, int64_t n0, WideSmem<FORM>& sm) {
+    using G = WideGeom<FORM>;
+    using ft = FT<FORM>;
+    constexpr int NP = G::NP, EB = G::EB, SLAB = G::SLAB, RD = G::RD, RS = G::RS, CPR = G::CPR;
+    constexpr int TM = G::TM, TN = G::TN, NTH = G::NTH, BM = G::BM, BN = G::BN, BK = G::BK;
+    constexpr int QCH = G::QCH, BCH = G::BCH, NSLAB = G::NSLAB;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / G::WGN, wn = wave % G::WGN;
+    const int lr = lane & 31, lh = lane >> 5;
+    const uint8_t* Ap[2] = {g.Aq, g.Aq1};
+    const uint8_t* Bp[2] = {(const uint8_t*)g.B0, (const uint8_t*)g.B1};
+    const int64_t AB = g.lda * EB, KB = (int64_t)g.K * EB;
+    const int64_t nb = g.K / 32;
+
+    // Buffer loads: a resource per operand piece based at the tile's first
+    // row, its range ending at the last row present (rows past it read as
+    // zero), a per-chunk lane offset that stays fixed, and the K tile's byte
+    // offset as the scalar offset.  K is a whole number of K tiles.
+    __amdgpu_buffer_rsrc_t ra[NP], rbs[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int64_t ar = g.F - m0 < BM ? g.F - m0 : BM, br = g.N - n0 < BN ? g.N - n0 : BN;
+        ra[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(Ap[p] + m0 * AB), (short)0,
+                                                  (int)(ar * AB), 0x00020000);
+        rbs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(Bp[p] + n0 * KB), (short)0,
+                                                   (int)(br * KB), 0x00020000);
+    }
+    uint32_t va[QCH], vb[BCH];
+#pragma unroll
+    for (int i = 0; i < QCH; ++i) {
+        const int c = tid + i * NTH;
+        va[i] = (uint32_t)((c / CPR) * AB + (c % CPR) * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < BCH; ++i) {
+        const int c = tid + i * NTH;
+        vb[i] = (uint32_t)((c / CPR) * KB + (c % CPR) * 16);
+    }
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+    struct Stage {
+        uint4 a[NP][QCH];
+        uint4 b[NP][BCH];
+        uint32_t sc[G::SCW];
+    };
+    // Block-scaled form: the 2 scale bytes of each row's 64-K tile (K % 128
+    // == 0), A rows then B rows, staged like the codes.
+    auto load_scales = [&](Stage& r, int k0) {
+        if constexpr (ft::MX) {
+            static_assert(G::ROWB == 64, "two scale bytes per row and K tile");
+#pragma unroll
+            for (int w = 0; w < G::SCW; ++w) {
+                const int row = tid + w * NTH;
+                uint32_t v = 0x7f7fu;
+                if (row < BM) {
+                    const int64_t f = m0 + row;
+                    if (f < g.F) v = *reinterpret_cast<const uint16_t*>(g.Aqs + f * nb + k0 / 32);
+                } else if (row < BM + BN) {
+                    const int64_t n = n0 + row - BM;
+                    if (n < g.N) v = *reinterpret_cast<const uint16_t*>((const uint8_t*)g.B1 + n * nb + k0 / 32);
+                }
+                r.sc[w] = v;
+            }
+        }
+    };
+    auto store_scales = [&](const Stage& r, int buf) {
+        if constexpr (ft::MX) {
+#pragma unroll
+            for (int w = 0; w < G::SCW; ++w)
+                if (tid + w * NTH < BM + BN) sm.mxs[buf][tid + w * NTH] = r.sc[w];
+        }
+    };
+    auto load = [&](Stage& r, int k0) {
+        const int32_t kb0 = k0 * EB;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int i = 0; i < QCH; ++i)
+                r.a[p][i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(ra[p], va[i], kb0, 0));
+#pragma unroll
+            for (int i = 0; i < BCH; ++i)
+                r.b[p][i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rbs[p], vb[i], kb0, 0));
+        }
+        load_scales(r, k0);
+    };
+    auto store = [&](const Stage& r, int buf) {
+        uint8_t* As = sm.tiles[buf];
+        uint8_t* Bs = sm.tiles[buf] + NP * BM * RS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int i = 0; i < QCH; ++i) {
+                const int c = tid + i * NTH, row = c / CPR, kc = c % CPR;
+                *reinterpret_cast<uint4*>(As + p * BM * RS + row * RS + kc * 16) = r.a[p][i];
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int c = tid + i * NTH, row = c / CPR, kc = c % CPR;
+                *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = r.b[p][i];
+            }
+        }
+        store_scales(r, buf);
+    };
+
+    f32x16 acc[TM][TN], acc2[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                acc[i][j][v] = 0.f;
+                if constexpr (FORM == FORM_FP16X3) acc2[i][j][v] = 0.f;
+            }
+
+    __syncthreads();
+    if constexpr (ft::SCALED) {
+        for (int i = tid; i < BM; i += NTH) sm.fsc[i] = m0 + i < g.F ? ldexpf(1.0f, g.fexp[m0 + i]) : 1.0f;
+    }
+    const int nk = (g.K + BK - 1) / BK;
+
+    {
+        // A software pipeline over units (slab s, MFMA block row bm) of every
+        // K tile.  The A fragment(s) of unit u + 2 and the B fragments of the
+        // next slab are read while unit u's products run; the next tile's LDS
+        // stores and the global loads of the tile after it are spread over the
+        // tile's first units; and the last two units' products are issued
+        // after the barrier, behind the reads of the next tile's first units,
+        // so the matrix units keep working across the barrier.  A fence after
+        // each unit keeps this order.  For the 64-K FP8 instruction an operand
+        // is two 16-byte reads, 32 bytes apart.  Split forms issue their three
+        // products (hi hi, hi lo, lo hi) per accumulator in that order, slab by
+        // slab, as the 128 x 128 tile does, so both give the same bits.
+        typedef int i32x4 __attribute__((ext_vector_type(4)));
+        using FragT = std::conditional_t<RD == 2, i32x8, uint4>;
+        constexpr int U = NSLAB * TM, NCH = NP * (QCH + BCH), CPU = (NCH + U - 3) / (U - 2);
+        static_assert(U % 4 == 0, "the A ring of 4 fragments wraps at tile boundaries");
+        auto rd = [&](const uint8_t* p) -> FragT {
+            if constexpr (RD == 2) {
+                const i32x4 lo = *reinterpret_cast<const i32x4*>(p);
+                const i32x4 hi = *reinterpret_cast<const i32x4*>(p + 32);
+                return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+            } else {
+                return *reinterpret_cast<const uint4*>(p);
+            }
+        };
+        FragT a[4][NP], b[2][TN][NP];
+        int sa[2][TM], sb[2][TN];
+        auto rdA = [&](int buf, int u, FragT (&d)[NP]) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                d[p] = rd(sm.tiles[buf] + p * BM * RS + ((wm * TM + u % TM) * 32 + lr) * RS + (u / TM) * SLAB + lh * 16);
+        };
+        auto rdB = [&](int buf, int sl, int par) {
+            const uint8_t* Bs = sm.tiles[buf] + NP * BM * RS;
+#pragma unroll
+            for (int bn = 0; bn < TN; ++bn)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    b[par][bn][p] = rd(Bs + p * BN * RS + ((wn * TN + bn) * 32 + lr) * RS + sl * SLAB + lh * 16);
+#pragma unroll
+            for (int x = 0; x < TM; ++x) sa[par][x] = 0x7f7f7f7f;
+#pragma unroll
+            for (int x = 0; x < TN; ++x) sb[par][x] = 0x7f7f7f7f;
+            if constexpr (ft::MX) {  // byte 2 sl + lh of the row's scale bytes: the lane half's 32-K block
+                const int sh = 8 * (2 * sl + lh);
+#pragma unroll
+                for (int x = 0; x < TM; ++x) sa[par][x] = (int)(sm.mxs[buf][(wm * TM + x) * 32 + lr] >> sh);
+#pragma unroll
+                for (int x = 0; x < TN; ++x) sb[par][x] = (int)(sm.mxs[buf][BM + (wn * TN + x) * 32 + lr] >> sh);
+            }
+        };
+        auto mf = [&](int u, int par) {
+            const int bm = u % TM;
+            constexpr int NTERM = NP == 2 ? 3 : 1;
+#pragma unroll
+            for (int term = 0; term < NTERM; ++term)
+#pragma unroll
+                for (int bn = 0; bn < TN; ++bn) {
+                    const FragT& x = a[u % 4][term == 2 ? 1 : 0];
+                    const FragT& y = b[par][bn][term == 1 ? 1 : 0];
+                    if constexpr (FORM == FORM_BF16 || FORM == FORM_BF16X3)
+                        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x),
+                                                                              __builtin_bit_cast(bf16x8, y), acc[bm][bn], 0, 0, 0);
+                    else if constexpr (FORM == FORM_FP16 || FORM == FORM_FP16X3) {
+                        // FP16X3: the cross terms carry the lo pieces' 2^11 and go to acc2.
+                        if (term == 0)
+                            acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x),
+                                                                                 __builtin_bit_cast(f16x8, y), acc[bm][bn], 0, 0, 0);
+                        else
+                            acc2[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x),
+                                                                                  __builtin_bit_cast(f16x8, y), acc2[bm][bn], 0, 0, 0);
+                    } else {  // FP8 E4M3 operands (formats 0/0) with unit or block scales
+                        acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[bm][bn], 0, 0, 0,
+                                                                                      sa[par][bm], 0, sb[par][bn]);
+                    }
+                }
+        };
+        // One K tile t in LDS buffer tt (tiles alternate buffers; the loop
+        // below is unrolled by two so that tt and every register index are
+        // compile-time constants).  On entry the reads of units 0 and 1 and of
+        // slab 0's B fragments are in flight; r holds tile t + 1.  At the last
+        // tile the stores, loads and next-tile reads repeat valid addresses
+        // and go unused.
+        Stage r;
+        auto tile = [&](int t, int tt) {
+            const int nbuf = tt ^ 1, par0 = (tt * NSLAB) & 1;
+            const int t2 = t + 2 < nk ? t + 2 : nk - 1;
+            const int32_t kb2 = t2 * BK * EB;
+#pragma unroll
+            for (int u = 0; u < U - 2; ++u) {
+                const int u2 = u + 2, s2 = u2 / TM;
+                if (u2 % TM == 0) rdB(tt, s2, (par0 + s2) & 1);
+                rdA(tt, u2, a[u2 % 4]);
+                // The next tile's LDS stores and the loads of the tile after
+                // it, CPU chunks per unit, each chunk's load reissued right
+                // after its store frees the registers.
+#pragma unroll
+                for (int cc = 0; cc < CPU; ++cc) {
+                    const int c = u * CPU + cc, p = c / (QCH + BCH), q = c % (QCH + BCH);
+                    if (c >= NCH) continue;
+                    if (q < QCH) {
+                        const int e = tid + q * NTH;
+                        *reinterpret_cast<uint4*>(sm.tiles[nbuf] + p * BM * RS + (e / CPR) * RS + (e % CPR) * 16) =
+                            r.a[p][q];
+                        r.a[p][q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(ra[p], va[q], kb2, 0));
+                    } else {
+                        const int e = tid + (q - QCH) * NTH;
+                        *reinterpret_cast<uint4*>(sm.tiles[nbuf] + NP * BM * RS + p * BN * RS + (e / CPR) * RS +
+                                                  (e % CPR) * 16) = r.b[p][q - QCH];
+                        r.b[p][q - QCH] =
+                            __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rbs[p], vb[q - QCH], kb2, 0));
+                    }
+                }
+                if constexpr (ft::MX) {
+                    if (u == 0) {
+                        store_scales(r, nbuf);
+                        load_scales(r, t2 * BK);
+                    }
+                }
+                mf(u, (par0 + u / TM) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            rdB(nbuf, 0, (par0 + NSLAB) & 1);
+            rdA(nbuf, 0, a[0]);
+            rdA(nbuf, 1, a[1]);
+            mf(U - 2, (par0 + NSLAB - 1) & 1);
+            mf(U - 1, (par0 + NSLAB - 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        load(r, 0);
+        store(r, 0);
+        load(r, (nk > 1 ? 1 : 0) * BK);
+        __syncthreads();
+        rdB(0, 0, 0);
+        rdA(0, 0, a[0]);
+        rdA(0, 1, a[1]);
+        for (int t = 0; t < nk; t += 2) {
+            tile(t, 0);
+            if (t + 1 < nk) tile(t + 1, 1);
+        }
+    }
+
+    // Epilogue: element v of block (bm, bn) is row 32 (wm TM + bm) + 8 (v >> 2) +
+    // 4 lh + (v & 3), column 32 (wn TN + bn) + lr of the tile.  Buffer stores
+    // on a resource that ends at the last frame (stores past it are dropped):
+    // the lane's row and column are its vector offset, the element's row
+    // offset (a compile-time multiple of the row stride) the scalar offset.
+    const float corr = (FORM == FORM_FP16X3) ? (1.0f / 2048.0f) : 1.0f;
+    const int64_t rows = g.F - m0 < BM ? g.F - m0 : BM;
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(g.out + m0 * g.ldo, (short)0,
+                                                                          (int)(rows * g.ldo * 4), 0x00020000);
+    const int rl = wm * TM * 32 + 4 * lh;  // the lane's first row in the tile
+    const int32_t ldo4 = (int32_t)g.ldo * 4;
+#pragma unroll
+    for (int bn = 0; bn < TN; ++bn) {
+        const int64_t col = n0 + (wn * TN + bn) * 32 + lr;
+        if (col >= g.N) continue;
+        int64_t oc = col;
+        if (g.real_pack) oc = col >= 2 ? col : (col == 0 ? 0 : (int64_t)g.N);
+        const uint32_t vo = (uint32_t)((rl * g.ldo + oc) * 4);
+#pragma unroll
+        for (int bm = 0; bm < TM; ++bm)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int rr = bm * 32 + 8 * (v >> 2) + (v & 3);
+                float val = acc[bm][bn][v];
+                if constexpr (FORM == FORM_FP16X3) val += acc2[bm][bn][v] * corr;
+                if constexpr (ft::SCALED) val *= sm.fsc[rl + rr];
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, val), ro, vo, rr * ldo4, 0);
+            }
+        if (g.real_pack && col < 2) {  // Im X_0, Im X_{P/2}
+#pragma unroll
+            for (int bm = 0; bm < TM; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int rr = bm * 32 + 8 * (v >> 2) + (v & 3);
+                    __builtin_amdgcn_raw_buffer_store_b32(0u, ro, vo + 4, rr * ldo4, 0);
+                }
+        }
+    }
+}
+
+template <int FORM>
+__global__ __launch_bounds__(WideGeom<FORM>::NTH) __attribute__((amdgpu_waves_per_eu(2)))
+void dft_gemm_wide_kernel(GemmArgs g) {
+    using G = WideGeom<FORM>;
+    __shared__ __attribute__((aligned(16))) WideSmem<FORM> sm;
+    const int64_t nm = (g.F + G::BM - 1) / G::BM, nn = (g.N + G::BN - 1) / G::BN;
+    const int64_t L = xcd_logical_block(blockIdx.x, (int64_t)gridDim.x);
+    const int64_t gsz_full = WIDE_GROUP_M * nn;
+    const int64_t grp = L / gsz_full, first_m = grp * WIDE_GROUP_M;
+    const int64_t gsz = min((int64_t)WIDE_GROUP_M, nm - first_m);
+    const int64_t within = L - grp * gsz_full;
+    gemm_tile_wide<FORM>(g, (first_m + within % gsz) * G::BM, (within / gsz) * G::BN, sm);
+}
+
 template <int FORM, int WN>
 __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     constexpr int BN = 64 * WN;
@@ -722,8 +1103,18 @@ hipError_t launch_form(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Raw-operand GEMM: wide tiles when K is a whole number of their K tiles (a
+// tile's byte range fits the 32-bit buffer offsets), else 128 x 128 tiles.
 template <int FORM>
 hipError_t launch_raw(const GemmArgs& g, hipStream_t s) {
+    using G = WideGeom<FORM>;
+    const int64_t eb = FT<FORM>::EB;
+    if (g.K % G::BK == 0 && g.lda == g.K && (int64_t)G::BM * g.lda * eb < (1ll << 31) &&
+        (int64_t)G::BN * g.K * eb < (1ll << 31)) {
+        const int64_t nm = (g.F + G::BM - 1) / G::BM, nn = (g.N + G::BN - 1) / G::BN;
+        hipLaunchKernelGGL((dft_gemm_wide_kernel<FORM>), dim3((unsigned)(nm * nn)), dim3(G::NTH), 0, s, g);
+        return hipGetLastError();
+    }
     constexpr int WN = 2, BN = 64 * WN;
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
     hipLaunchKernelGGL((dft_gemm_raw_kernel<FORM, WN>), dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
