@@ -139,10 +139,13 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
     }
     if (qmode_frame_scaled(a.qmode)) {
         // Per-frame scaled codes: the frame's maximum must be known before its
-        // first code is written, and a frame spans many blocks.  Pass 1 finds
-        // the partial maxima, a small kernel the exponents, and pass 2
-        // recomputes the FIR (reading the input again is cheaper than writing
-        // and reading FP32 rows) and writes the scaled codes.
+        // first code is written.  Frames of at most 4096 floats: one block
+        // holds whole frame rows and does it in one pass over the input.
+        // Wider frames span many blocks: pass 1 finds the partial maxima, a
+        // small kernel the exponents, and pass 2 recomputes the FIR (reading
+        // the input again is cheaper than writing and reading FP32 rows) and
+        // writes the scaled codes.
+        if (fir_frame_vec(a) != 0) return launch_fir_frame(a, s);
         if (!a.amax || !a.fexp || !a.q || (a.qmode == QM_FP16FX2 && !a.q1)) return hipErrorInvalidValue;
         FirArgs p1 = a;
         p1.qmode = QM_AMAXONLY;

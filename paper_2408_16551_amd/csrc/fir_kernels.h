@@ -48,6 +48,14 @@ FirTune fir_tune();
 // Vector width (floats per thread) for these arguments.
 int pick_vec(const FirArgs& a);
 
+// Single-pass FIR for the per-frame scaled forms (fir_frame.hip): whole frame
+// rows per block, so the frame's maximum, exponent and codes come from one
+// read of the input.  fir_frame_vec: the floats per thread it would use, or 0
+// when the arguments need the three-launch path (frames wider than 4096
+// floats, more taps than its register ring holds, misaligned buffers).
+int fir_frame_vec(const FirArgs& a);
+hipError_t launch_fir_frame(const FirArgs& a, hipStream_t s);
+
 // Per-mode entry points (fir_out_*.hip).
 hipError_t launch_fir_mode_f32(FirArgs& a, int vec, hipStream_t s);
 hipError_t launch_fir_mode_mx(FirArgs& a, int vec, hipStream_t s);
@@ -277,6 +285,49 @@ __device__ __forceinline__ void fir_amax(const FirArgs& a, const typename VecT<V
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
+// Row u of a block in a per-frame scaled operand form, the frame's values
+// times 2^-e: FP8 E4M3 codes saturated at 448 (packed as the block-scaled
+// codes are), fp16, or fp16 hi + lo with lo = RNE((x - hi) 2^11).
+template <int VEC, int QM, class Sink>
+__device__ __forceinline__ void fir_store_frame(const typename VecT<VEC>::T& acc, int e, int col, const Sink& out,
+                                                int u) {
+    const float sc = ldexpf(1.0f, -e);
+    if constexpr (QM == QM_FP8F) {
+        float x[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) x[v] = fminf(fmaxf(vget<VEC>(acc, v) * sc, -448.0f), 448.0f);
+        if constexpr (VEC == 4) {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
+            out.q(0, u, (uint32_t)w);
+        } else if constexpr (VEC == 2) {
+            const uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false) & 0xffffu;
+            const uint32_t w1 = dpp_read<0xF5>(w);
+            if ((col & 1) == 0) out.q(0, u, w | (w1 << 16));
+        } else {
+            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false) & 0xffu;
+            const uint32_t c1 = dpp_read<0x55>(c), c2 = dpp_read<0xAA>(c), c3 = dpp_read<0xFF>(c);
+            if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
+        }
+    } else {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const float x = vget<VEC>(acc, v) * sc;
+            const _Float16 h = (_Float16)x;
+            hi[v] = __builtin_bit_cast(uint16_t, h);
+            lo[v] = __builtin_bit_cast(uint16_t, (_Float16)((x - (float)h) * 2048.0f));
+        }
+        auto put = [&](int piece, const uint32_t (&h)[4]) {
+            if constexpr (VEC == 4) out.q(piece, u, (uint64_t)(h[0] | (h[1] << 16)) | ((uint64_t)(h[2] | (h[3] << 16)) << 32));
+            else if constexpr (VEC == 2) out.q(piece, u, h[0] | (h[1] << 16));
+            else out.q(piece, u, (uint16_t)h[0]);
+        };
+        put(0, hi);
+        if constexpr (QM == QM_FP16FX2) put(1, lo);
+    }
+}
+
 // Store row u of a block: FP32, the frame row's partial maxima only,
 // or an operand form (QM):
 //  - QM_MX, block-scaled FP8: the 32/VEC lanes that hold one 32-float block
@@ -315,42 +366,8 @@ __device__ __forceinline__ void fir_store(const FirArgs& a, const typename VecT<
             if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
         }
         if ((col & (GL - 1)) == 0) out.s8(u, (uint8_t)(e + 127));
-    } else if constexpr (QM == QM_FP8F) {
-        // The frame's scale, then the same packing as the block-scaled codes.
-        const float sc = ldexpf(1.0f, -a.fexp[f]);
-        float x[4];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) x[v] = fminf(fmaxf(vget<VEC>(acc, v) * sc, -448.0f), 448.0f);
-        if constexpr (VEC == 4) {
-            int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
-            w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w, true);
-            out.q(0, u, (uint32_t)w);
-        } else if constexpr (VEC == 2) {
-            const uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false) & 0xffffu;
-            const uint32_t w1 = dpp_read<0xF5>(w);
-            if ((col & 1) == 0) out.q(0, u, w | (w1 << 16));
-        } else {
-            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[0], 0, false) & 0xffu;
-            const uint32_t c1 = dpp_read<0x55>(c), c2 = dpp_read<0xAA>(c), c3 = dpp_read<0xFF>(c);
-            if ((col & 3) == 0) out.q(0, u, c | (c1 << 8) | (c2 << 16) | (c3 << 24));
-        }
-    } else if constexpr (QM == QM_FP16F || QM == QM_FP16FX2) {
-        const float sc = ldexpf(1.0f, -a.fexp[f]);
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            const float x = vget<VEC>(acc, v) * sc;
-            const _Float16 h = (_Float16)x;
-            hi[v] = __builtin_bit_cast(uint16_t, h);
-            lo[v] = __builtin_bit_cast(uint16_t, (_Float16)((x - (float)h) * 2048.0f));
-        }
-        auto put = [&](int piece, const uint32_t (&h)[4]) {
-            if constexpr (VEC == 4) out.q(piece, u, (uint64_t)(h[0] | (h[1] << 16)) | ((uint64_t)(h[2] | (h[3] << 16)) << 32));
-            else if constexpr (VEC == 2) out.q(piece, u, h[0] | (h[1] << 16));
-            else out.q(piece, u, (uint16_t)h[0]);
-        };
-        put(0, hi);
-        if constexpr (QM == QM_FP16FX2) put(1, lo);
+    } else if constexpr (QM == QM_FP8F || QM == QM_FP16F || QM == QM_FP16FX2) {
+        fir_store_frame<VEC, QM>(acc, a.fexp[f], col, out, u);
     } else if constexpr (QM == QM_AMAXONLY) {
         fir_amax<VEC>(a, acc, f, col, gw);
     } else if constexpr (QM == QM_BF16 || QM == QM_BF16X2) {

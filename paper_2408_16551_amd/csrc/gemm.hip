@@ -764,22 +764,35 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
         uint32_t sc[G::SCW];
     };
     // Block-scaled form: the 2 scale bytes of each row's 64-K tile (K % 128
-    // == 0), A rows then B rows, staged like the codes.
+    // == 0), A rows then B rows, staged like the codes.  When a row's scales
+    // are a whole number of 16-byte groups (K % 512 == 0), a group -- the
+    // scales of 8 K tiles -- is loaded once into registers and each tile takes
+    // its 2 bytes from there: row-strided 2-byte loads per tile cost as much
+    // L2 traffic (a cache line per row) as half the codes.
+    uint4 scg[G::SCW];
+    const bool sc_grouped = nb % 16 == 0;
     auto load_scales = [&](Stage& r, int k0) {
         if constexpr (ft::MX) {
             static_assert(G::ROWB == 64, "two scale bytes per row and K tile");
+            const int kt = k0 / 64;  // K tile index
 #pragma unroll
             for (int w = 0; w < G::SCW; ++w) {
                 const int row = tid + w * NTH;
-                uint32_t v = 0x7f7fu;
+                const uint8_t* src = nullptr;
                 if (row < BM) {
-                    const int64_t f = m0 + row;
-                    if (f < g.F) v = *reinterpret_cast<const uint16_t*>(g.Aqs + f * nb + k0 / 32);
+                    if (m0 + row < g.F) src = g.Aqs + (m0 + row) * nb;
                 } else if (row < BM + BN) {
-                    const int64_t n = n0 + row - BM;
-                    if (n < g.N) v = *reinterpret_cast<const uint16_t*>((const uint8_t*)g.B1 + n * nb + k0 / 32);
+                    if (n0 + row - BM < g.N) src = (const uint8_t*)g.B1 + (n0 + row - BM) * nb;
                 }
-                r.sc[w] = v;
+                if (sc_grouped) {
+                    if ((kt & 7) == 0)
+                        scg[w] = src ? *reinterpret_cast<const uint4*>(src + kt * 2) : make_uint4(~0u, ~0u, ~0u, ~0u);
+                    const int q = (kt & 7) >> 1;
+                    const uint32_t word = q == 0 ? scg[w].x : q == 1 ? scg[w].y : q == 2 ? scg[w].z : scg[w].w;
+                    r.sc[w] = src ? (word >> (16 * (kt & 1))) & 0xffffu : 0x7f7fu;
+                } else {
+                    r.sc[w] = src ? *reinterpret_cast<const uint16_t*>(src + kt * 2) : 0x7f7fu;
+                }
             }
         }
     };
@@ -969,9 +982,14 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
             mf(U - 1, (par0 + NSLAB - 1) & 1);
             __builtin_amdgcn_sched_barrier(0);
         };
-        load(r, 0);
-        store(r, 0);
-        load(r, (nk > 1 ? 1 : 0) * BK);
+        {
+            // Both first tiles' loads in flight together: one memory latency
+            // before the first products, not two.
+            Stage r0;
+            load(r0, 0);
+            load(r, (nk > 1 ? 1 : 0) * BK);
+            store(r0, 0);
+        }
         __syncthreads();
         rdB(0, 0, 0);
         rdA(0, 0, a[0]);
