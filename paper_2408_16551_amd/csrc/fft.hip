@@ -226,6 +226,141 @@ __global__ __launch_bounds__(256) void fft_dft_kernel(const float* __restrict__ 
     }
 }
 
+// Complex frames with P = Q * Q, Q = 64 (P = 4096): the same three steps with
+// both DFT matrices held in registers and every product on
+// v_mfma_f32_32x32x2_f32.  Four waves share a frame.  Step 1: wave w computes
+// rows k1 = 16 w .. 16 w + 15 (real and imaginary parts: 32 realified rows) of
+// C = DFT_Q Y over all Q columns p2; its slice of the realified DFT matrix (Q
+// floats per lane) is loaded once per launch.  The summed index is ordered
+// (p1, re/im), so each MFMA's B operand is 64 consecutive floats of the frame
+// as it lies in memory (and in LDS: no transposition, no bank conflicts).
+// The real and imaginary parts of an output land in one lane, which applies
+// the twiddle W_P^{p2 k1} (its Q / 2 twiddles are also kept in registers).
+// Step 3: wave w computes columns k2 = 16 w .. 16 w + 15 (real and imaginary:
+// 32 realified columns) of X = A' DFT_Q over all Q rows k1, its slice of the
+// realified matrix again in registers, A' read from LDS (row stride 2 Q + 2
+// floats: conflict-free).  The next frame's input is loaded into registers
+// during step 1 and stored to LDS before step 3.
+constexpr int kFq = 64;                     // Q
+constexpr int kFqS = 2 * kFq + 2;           // A' row stride (floats)
+constexpr int kFqLds = 4 * (2 * kFq * kFq + kFq * kFqS);
+
+__global__ __launch_bounds__(256) void fft_q64_kernel(const float* __restrict__ y, int64_t ldy, int64_t F,
+                                                      const float* __restrict__ tw, float* __restrict__ out,
+                                                      int64_t ldo) {
+    constexpr int Q = kFq, P = Q * Q;
+    typedef float f32x16 __attribute__((ext_vector_type(16)));
+    extern __shared__ float lds[];
+    float* Yb = lds;              // the frame: complex samples p1 Q + p2, re then im
+    float* As = lds + 2 * P;      // A'[k1][p2] as (re, im), row stride kFqS
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+
+    // Step-1 operand A[row][k]: row = (part r / 16, k1 = 16 w + r % 16), k =
+    // (p1 = j, h): Re rows take (cos, sin), Im rows (-sin, cos) of 2 pi k1 p1 / Q.
+    // Step-3 operand B[k][col]: k = (p2 = j, h), col = (part r / 16, k2 = 16 w
+    // + r % 16): Re columns take (cos, sin), Im columns (-sin, cos).  With
+    // P = Q^2 the angle 2 pi m / Q is table entry m Q of the P-point table.
+    float a1[Q], b3[Q];
+    {
+        const int x = 16 * w + (r & 15);  // k1 of the step-1 row, k2 of the step-3 column
+        const bool im = r >= 16;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            const int m = (x * j) & (Q - 1);
+            const float c = tw[2 * m * Q], sn = tw[2 * m * Q + 1];
+            const float v = im ? (h ? c : -sn) : (h ? sn : c);
+            a1[j] = v;
+            b3[j] = v;
+        }
+    }
+    // Twiddles of the lane's step-1 outputs: column block nb, element v < 8
+    // holds (re, im) at (v, v + 8) for k1 = 16 w + 8 (v / 4) + 4 h + v % 4,
+    // p2 = 32 nb + r.
+    float twc[2][8], tws[2][8];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int k1 = 16 * w + 8 * (v >> 2) + 4 * h + (v & 3), p2 = 32 * nb + r;
+            const int idx = (p2 * k1) & (P - 1);
+            twc[nb][v] = tw[2 * idx];
+            tws[nb][v] = tw[2 * idx + 1];
+        }
+
+    // Frame loads: 2 P floats = 512 float4, two per thread.
+    float4 pre[8];
+    auto load_frame = [&](int64_t f) {
+        const float4* src = reinterpret_cast<const float4*>(y + f * ldy);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pre[i] = src[tid + 256 * i];
+    };
+    auto store_frame = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) reinterpret_cast<float4*>(Yb)[tid + 256 * i] = pre[i];
+    };
+
+    int64_t f = blockIdx.x;
+    if (f < F) {
+        load_frame(f);
+        store_frame();
+    }
+    __syncthreads();
+    for (; f < F; f += gridDim.x) {
+        const int64_t fn = f + gridDim.x;
+        if (fn < F) load_frame(fn);
+
+        // Step 1: two 32 x 32 column blocks, Q MFMAs each over k = (p1, re/im).
+        f32x16 c1[2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) c1[nb][v] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const float bv = Yb[(j * Q + 32 * nb + r) * 2 + h];
+                c1[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], bv, c1[nb], 0, 0, 0);
+            }
+        // Twiddle and write A'[k1][p2].
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const float cr = c1[nb][v], ci = c1[nb][v + 8];
+                const float wc = twc[nb][v], ws = tws[nb][v];
+                const int k1 = 16 * w + 8 * (v >> 2) + 4 * h + (v & 3), p2 = 32 * nb + r;
+                *reinterpret_cast<float2*>(As + k1 * kFqS + 2 * p2) =
+                    make_float2(cr * wc + ci * ws, ci * wc - cr * ws);  // (cr + i ci)(wc - i ws)
+            }
+        __syncthreads();  // A' complete; every wave is done with the frame in Yb
+        if (fn < F) store_frame();
+
+        // Step 3: two 32 x 32 row blocks (k1), Q MFMAs each over k = (p2, re/im).
+        f32x16 x3[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) x3[rb][v] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const float av = As[(32 * rb + r) * kFqS + 2 * j + h];
+                x3[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b3[j], x3[rb], 0, 0, 0);
+            }
+        // X[k1 + Q k2]: element v of row block rb is k1 = 32 rb + 8 (v / 4) +
+        // 4 h + v % 4, the lane's column (part r / 16, k2 = 16 w + r % 16).
+        float* of = out + f * ldo + 2 * (Q * (16 * w + (r & 15))) + (r >> 4);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) of[2 * (32 * rb + 8 * (v >> 2) + 4 * h + (v & 3))] = x3[rb][v];
+        __syncthreads();  // the next frame is in Yb; every wave is done with A'
+    }
+}
+
 template <int P1, int P2, bool CPLX>
 hipError_t launch_fft_t(const FftArgs& a, hipStream_t s) {
     using S = FftShape<P1, P2, CPLX>;
@@ -279,6 +414,20 @@ hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStre
 
 hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s) {
     if (a.F <= 0) return hipSuccess;
+    if (a.cplx && a.P == kFq * kFq && a.ldy % 4 == 0 && ((uintptr_t)a.y & 15) == 0) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void*)fft_q64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               kFqLds);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        int64_t grid = 2 * (int64_t)a.cus;  // two blocks per CU (65.5 KiB of LDS each)
+        if (grid > a.F) grid = a.F;
+        hipLaunchKernelGGL(fft_q64_kernel, dim3((unsigned)grid), dim3(256), kFqLds, s, a.y, a.ldy, a.F, a.tw, a.out,
+                           a.ldo);
+        return hipGetLastError();
+    }
     switch (a.P) {
         case 256: return a.cplx ? launch_fft_t<16, 16, true>(a, s) : launch_fft_t<16, 16, false>(a, s);
         case 512: return a.cplx ? launch_fft_t<32, 16, true>(a, s) : launch_fft_t<32, 16, false>(a, s);

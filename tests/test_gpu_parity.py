@@ -326,9 +326,9 @@ def test_factored_dft_matches_oracle(oracle, P, M, cplx, frames):
         assert np.all(X[:, 0].imag == 0) and np.all(X[:, -1].imag == 0)
 
 
-def test_factored_dft_streaming_bitwise():
+@pytest.mark.parametrize("P,M", [(1024, 12), (4096, 8)])
+def test_factored_dft_streaming_bitwise(P, M):
     from paper_2408_16551_amd.pfb import Plan, State
-    P, M = 1024, 12
     N = P * 90 + 77
     x = _rand(N, True, seed=5)
     plan = Plan(P, M, "c64", "hann", "fp32", dft="factored")
