@@ -8,7 +8,8 @@
  * consecutive chunks of one signal: the concatenated outputs equal the
  * filter bank of the concatenated inputs.
  *
- * A server thread runs steps back to back.  Requests queue in arrival order
+ * A server thread runs steps back to back, building and enqueuing the next
+ * step while the previous one is still on the device.  Requests queue in arrival order
  * and are admitted while a slot is free and their device buffers (input and
  * output) fit the HBM budget; a stream runs one request at a time, in order.
  * Each step gives every admitted request whose input has reached the device
@@ -147,6 +148,55 @@ tina_status tina_server_get_stats(tina_server_t server, tina_server_stats* stats
  * out[i] = 1 if released, else 0.  *final_used = bytes allocated at the end. */
 tina_status tina_server_arena_simulate(int64_t capacity, const int64_t* ops, int32_t n, int64_t* out,
                                        int64_t* final_used);
+
+/* Host-only run of the server's scheduler on a scripted sequence of
+ * operations, exposed for tests; no device work.  The decisions are those of
+ * the running server: admission in arrival order while a slot is free and the
+ * buffers fit the arena (a stream runs one request at a time; a request that
+ * does not fit blocks the ones behind it), per-step quotas (frames_per_step
+ * times max(1, max_active / ready requests) frames per request), cancellation
+ * of the newest queued request of a stream, steps completing or failing in
+ * order.  Requests are complex64 (8 bytes per sample and per output value).
+ *
+ * ops[i].kind and its fields:
+ *   ADD_STREAM  arg = channels P                 -> event (ADD_STREAM, id = stream id, a = P)
+ *   SUBMIT      arg = stream id, value = samples (negative: device buffers,
+ *               -value samples, no arena)         -> event (SUBMIT, status, id (0 if refused),
+ *                                                    a = samples, b = frames of the request)
+ *   ADMIT       run admission                      -> one event (ADMIT, id, a = arena offset of
+ *                                                    the input, b = of the output; -1 for device)
+ *   READY       value = request id: its input copy completed (device-buffer
+ *               requests are ready on admission)   -> event (READY, status)
+ *   STEP        complete admitted empty requests, then build a step and put
+ *               it in flight                       -> (COMPLETE ...) for empty requests, one
+ *                                                    event (STEP, id, a = samples, b = frames)
+ *                                                    per item, then (STEP, id = 0, a = items,
+ *                                                    b = steps in flight)
+ *   COMPLETE    arg = TINA_OK or the status the oldest in-flight step fails
+ *               with                               -> (COMPLETE, status, id, a = frames done,
+ *                                                    b = steps) for every request it ends
+ *   CANCEL      value = request id                 -> event (CANCEL, status: OK, NOT_READY
+ *                                                    (already admitted) or INVALID_ARGUMENT)
+ * Up to `capacity` events are written; *n_events receives the number there
+ * were (TOO_LARGE if more than capacity). */
+enum {
+    TINA_SCHED_ADD_STREAM = 1, TINA_SCHED_SUBMIT = 2, TINA_SCHED_ADMIT = 3, TINA_SCHED_READY = 4,
+    TINA_SCHED_STEP = 5, TINA_SCHED_COMPLETE = 6, TINA_SCHED_CANCEL = 7
+};
+typedef struct tina_sched_op {
+    int32_t kind;
+    int32_t arg;
+    int64_t value;
+} tina_sched_op;
+typedef struct tina_sched_event {
+    int32_t kind;
+    int32_t status;
+    uint64_t id;
+    int64_t a, b;
+} tina_sched_event;
+tina_status tina_server_schedule_simulate(int32_t max_active, int32_t max_queued, int64_t frames_per_step,
+                                          int64_t arena_bytes, const tina_sched_op* ops, int32_t n_ops,
+                                          tina_sched_event* events, int32_t capacity, int32_t* n_events);
 
 #ifdef __cplusplus
 }

@@ -84,27 +84,49 @@ struct tina_pfb_batch_s {
     int64_t amax_floats = 0;
     int32_t* fexp = nullptr;     // per-frame scale exponents (scaled forms), amax_floats entries
     BatchTable* d_table = nullptr;
-    BatchTable* h_table = nullptr;  // pinned
+    // Two pinned host tables used in turn: a call fills one while the upload
+    // of the other may still be pending, so a caller can build the next step
+    // while the previous one runs.  table_free[k]: the last upload from
+    // h_tables[k] has completed.
+    BatchTable* h_tables[2] = {nullptr, nullptr};
+    BatchTable* h_table = nullptr;  // the table being filled / launched
+    int next_table = 0;
     size_t table_bytes = 0;
-    hipEvent_t table_free = nullptr;  // the last upload from h_table has completed
-    bool table_pending = false;
+    hipEvent_t table_free[2] = {nullptr, nullptr};
+    bool table_pending[2] = {false, false};
     Tune tune;
     bool have_tune = false;
-    // Captured step graphs (table upload + three persistent launches), keyed by
-    // the kernel variant: tap ring, exact taps, launch shape.
-    std::map<std::string, hipGraphExec_t> graphs;
-    int64_t graph_gemm_grid = 0;  // fixed GEMM grid of captured steps (0: no graphs)
+    // Captured step graphs (the launches of one step; the table upload stays
+    // outside), keyed by the kernel variant: tap ring, exact taps, launch
+    // shape.  gemm_node: the GEMM launch, whose grid is set to each step's own
+    // tile count before the replay.
+    struct StepGraph {
+        hipGraph_t graph = nullptr;  // kept: its nodes name the executable graph's nodes
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t gemm_node = nullptr;
+        hipKernelNodeParams gemm_params{};
+    };
+    std::map<std::string, StepGraph> graphs;
+    int64_t graph_gemm_grid = 0;  // GEMM grid the step graphs are captured with (0: no graphs)
     StreamOrder order;            // every call shares ws, amax, fexp and d_table
 
     void release() {
         order.release();
-        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto& kv : graphs) {
+            (void)hipGraphExecDestroy(kv.second.exec);
+            (void)hipGraphDestroy(kv.second.graph);
+        }
         graphs.clear();
-        if (table_free) (void)hipEventDestroy(table_free);
-        if (h_table) (void)hipHostFree(h_table);
+        for (int k = 0; k < 2; ++k) {
+            if (table_free[k]) (void)hipEventDestroy(table_free[k]);
+            if (h_tables[k]) (void)hipHostFree(h_tables[k]);
+            table_free[k] = nullptr;
+            h_tables[k] = nullptr;
+        }
+        h_table = nullptr;
         for (void* p : {(void*)ws, (void*)amax, (void*)fexp, (void*)d_table})
             if (p) (void)hipFree(p);
-        table_free = nullptr; h_table = nullptr; ws = nullptr; amax = nullptr; fexp = nullptr; d_table = nullptr;
+        ws = nullptr; amax = nullptr; fexp = nullptr; d_table = nullptr;
     }
 };
 
@@ -334,30 +356,46 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
 }
 
 // The captured step graph of one kernel variant (tap ring, exact taps,
-// launch shape), captured and instantiated on first use.
+// launch shape), captured and instantiated on first use.  The GEMM launch is
+// found among the graph's kernel nodes by its grid (graph_gemm_grid is kept
+// apart from the fixed grids of the other stages).
 tina_status step_graph(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
-                       hipGraphExec_t& exec) {
+                       tina_pfb_batch_s::StepGraph*& out) {
     const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
                             std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipMemcpyAsync(b->d_table, b->h_table, b->table_bytes, hipMemcpyHostToDevice, s);
-        tina_status st =
-            e == hipSuccess ? launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid) : TINA_ERR_DEVICE;
+        tina_status st = launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid);
         hipError_t e2 = hipStreamEndCapture(s, &graph);
-        if (e != hipSuccess || st != TINA_OK || e2 != hipSuccess) {
+        if (st != TINA_OK || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return fail(TINA_ERR_DEVICE, "batch: step graph capture failed");
         }
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return fail(TINA_ERR_DEVICE, std::string("batch: graph instantiate: ") + hipGetErrorString(e));
-        it = b->graphs.emplace(key, ex).first;
+        tina_pfb_batch_s::StepGraph sg;
+        size_t nn = 0;
+        hipError_t e = hipGraphGetNodes(graph, nullptr, &nn);
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (e == hipSuccess && nn > 0) e = hipGraphGetNodes(graph, nodes.data(), &nn);
+        for (size_t i = 0; e == hipSuccess && i < nn; ++i) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nodes[i], &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(nodes[i], &kp) == hipSuccess && (int64_t)kp.gridDim.x == b->graph_gemm_grid) {
+                sg.gemm_node = nodes[i];
+                sg.gemm_params = kp;
+            }
+        }
+        e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(TINA_ERR_DEVICE, std::string("batch: graph instantiate: ") + hipGetErrorString(e));
+        }
+        sg.graph = graph;
+        it = b->graphs.emplace(key, sg).first;
     }
-    exec = it->second;
+    out = &it->second;
     return TINA_OK;
 }
 
@@ -365,31 +403,51 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
                       const std::vector<int64_t>& frames, bool use_graph = false) {
     const std::vector<GroupPlan> groups = make_groups(b, w, frames, n);
     use_graph = use_graph && groups.size() == 1;
+    // Launch errors are read with hipGetLastError: a status left by an earlier
+    // query of a pending event (hipErrorNotReady) must not be read as one.
+    (void)hipGetLastError();
     HIP_TRY(b->order.begin(s));
     for (const GroupPlan& g : groups) {
-        if (b->table_pending) {
-            HIP_TRY(hipEventSynchronize(b->table_free));  // host copy of the table is free again
-            b->table_pending = false;
+        const int k = b->next_table;
+        b->next_table ^= 1;
+        if (b->table_pending[k]) {
+            HIP_TRY(hipEventSynchronize(b->table_free[k]));  // this host table's last upload is done
+            b->table_pending[k] = false;
         }
+        b->h_table = b->h_tables[k];
         int max_m = 1;
         bool all_exact = true;
         fill_table(b, w, frames, g, tune, dry, max_m, all_exact);
-        const bool graph_ok = use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid;
-        if (graph_ok) {
-            // Fixed topology: the full-size table upload and all three launches
-            // (a stage with no units returns at once), so one graph per kernel
-            // variant serves every step.
-            hipGraphExec_t exec = nullptr;
-            tina_status st = step_graph(b, s, tune, max_m, all_exact, exec);
+        HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(b->table_free[k], s));
+        b->table_pending[k] = true;
+        tina_pfb_batch_s::StepGraph* sg = nullptr;
+        if (use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid) {
+            tina_status st = step_graph(b, s, tune, max_m, all_exact, sg);
             if (st != TINA_OK) return st;
-            HIP_TRY(hipGraphLaunch(exec, s));
+            if (sg->gemm_node) {  // this step's GEMM grid: blocks past the tiles' ranges would only return
+                hipKernelNodeParams kp = sg->gemm_params;
+                kp.gridDim.x = (unsigned)gemm_grid(b->h_table);
+                if (hipGraphExecKernelNodeSetParams(sg->exec, sg->gemm_node, &kp) != hipSuccess) {
+                    // Replays keep the captured (largest) grid from now on; the
+                    // failed call's error is cleared so later launches do not
+                    // report it.
+                    (void)hipGetLastError();
+                    sg->gemm_params.gridDim.x = (unsigned)b->graph_gemm_grid;
+                    (void)hipGraphExecKernelNodeSetParams(sg->exec, sg->gemm_node, &sg->gemm_params);
+                    (void)hipGetLastError();
+                    sg->gemm_node = nullptr;
+                }
+            }
+        }
+        if (sg) {
+            // Fixed topology: all three launches (a stage with no units returns
+            // at once), so one graph per kernel variant serves every step.
+            HIP_TRY(hipGraphLaunch(sg->exec, s));
         } else {
-            HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
             tina_status st = launch_stages(b, s, tune, max_m, all_exact, false);
             if (st != TINA_OK) return st;
         }
-        HIP_TRY(hipEventRecord(b->table_free, s));
-        b->table_pending = true;
         if (!dry) {
             for (int i = 0; i < g.count; ++i) {
                 tina_pfb_work& it = w[g.first + i];
@@ -429,7 +487,9 @@ std::string signature(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<i
 // fixes the grid of the captured step graphs (the cost-balanced split may give
 // one XCD up to all of them).
 void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
-    b->graph_gemm_grid = 8 * std::max<int64_t>(max_gemm_tiles, 1);
+    int64_t g = 8 * std::max<int64_t>(max_gemm_tiles, 1);
+    while (g == (int64_t)b->cus * 4 || g == (int64_t)b->cus * 2) g += 8;  // unlike every other stage's grid
+    b->graph_gemm_grid = g;
 }
 
 // Used by the server: run one step's items, through the cached step graph
@@ -458,8 +518,8 @@ tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s) {
     const Tune tune;
     for (int mt = 1; mt <= 64; mt *= 2)
         for (int exact = 1; exact >= (mt == 1 ? 1 : 0); --exact) {
-            hipGraphExec_t exec = nullptr;
-            tina_status st = step_graph(b, s, tune, mt, exact != 0, exec);
+            tina_pfb_batch_s::StepGraph* sg = nullptr;
+            tina_status st = step_graph(b, s, tune, mt, exact != 0, sg);
             if (st != TINA_OK) return st;
         }
     return TINA_OK;
@@ -512,10 +572,13 @@ tina_status tina_pfb_batch_create(int device, int precision, int max_items, int6
             return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: scale workspace");
     }
     if (hipMalloc(&b->d_table, b->table_bytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: table");
-    if (hipHostMalloc(&b->h_table, b->table_bytes, hipHostMallocDefault) != hipSuccess)
-        return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: pinned table");
-    if (hipEventCreateWithFlags(&b->table_free, hipEventDisableTiming) != hipSuccess)
-        return bail(TINA_ERR_DEVICE, "batch_create: event");
+    for (int k = 0; k < 2; ++k) {
+        if (hipHostMalloc(&b->h_tables[k], b->table_bytes, hipHostMallocDefault) != hipSuccess)
+            return bail(TINA_ERR_OUT_OF_MEMORY, "batch_create: pinned table");
+        if (hipEventCreateWithFlags(&b->table_free[k], hipEventDisableTiming) != hipSuccess)
+            return bail(TINA_ERR_DEVICE, "batch_create: event");
+    }
+    b->h_table = b->h_tables[0];
     *out = b;
     return TINA_OK;
 }

@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -28,6 +29,7 @@
 #include <vector>
 
 #include "runtime_types.h"
+#include "scheduler.h"
 #include "tina_pfb_batch.h"
 #include "tina_pfb_server.h"
 
@@ -35,88 +37,31 @@ using namespace tina;
 
 namespace {
 
-// First-fit allocator over [0, capacity) in 256-byte units of alignment,
-// coalescing neighbours on release.  Host-side bookkeeping only.
-class Arena {
-  public:
-    void init(int64_t cap) {
-        cap_ = cap;
-        free_.clear();
-        sizes_.clear();
-        if (cap > 0) free_[0] = cap;
-        used_ = high_ = 0;
-    }
-    static int64_t round(int64_t n) { return ((n + 255) / 256) * 256; }
-    int64_t alloc(int64_t n) {
-        n = round(n < 1 ? 1 : n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                const int64_t off = it->first, rem = it->second - n;
-                free_.erase(it);
-                if (rem > 0) free_[off + n] = rem;
-                sizes_[off] = n;
-                used_ += n;
-                high_ = std::max(high_, used_);
-                return off;
-            }
-        }
-        return -1;
-    }
-    bool release(int64_t off) {
-        auto s = sizes_.find(off);
-        if (s == sizes_.end()) return false;
-        int64_t n = s->second;
-        sizes_.erase(s);
-        used_ -= n;
-        int64_t start = off;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && next->first == off + n) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                start = prev->first;
-                n += prev->second;
-                free_.erase(prev);
-            }
-        }
-        free_[start] = n;
-        return true;
-    }
-    int64_t used() const { return used_; }
-    int64_t high() const { return high_; }
-    int64_t capacity() const { return cap_; }
-
-  private:
-    int64_t cap_ = 0, used_ = 0, high_ = 0;
-    std::map<int64_t, int64_t> free_;
-    std::unordered_map<int64_t, int64_t> sizes_;
-};
-
-enum Phase { QUEUED, ACTIVE, DRAINING, DONE };
-
-struct Req {
-    uint64_t id = 0;
+// The server's side of a request: the caller's request and the events of its
+// copies.  The scheduler's Request (sched::Request::user) points here.
+struct ReqX {
     tina_request r{};
-    int64_t frames_total = 0;
-    int64_t in_bytes = 0, out_bytes = 0, row_bytes = 0, sample_bytes = 0;
-    int64_t off_in = -1, off_out = -1;
-    int64_t samples_done = 0, frames_done = 0;
-    bool in_ready = false;
+    int64_t sample_bytes = 0, row_bytes = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    Phase phase = QUEUED;
-    tina_result res{};
+    std::string fail_msg;  // why a step of this request failed
 };
 
-struct LStream {
-    tina_pfb_plan_s* plan = nullptr;
-    tina_pfb_state_s* state = nullptr;
-    int64_t submitted_residue = 0;  // residue after every submitted request
-    bool busy = false;              // a request of this stream is admitted
-    std::vector<uint64_t> queued;   // its queued requests, oldest first
+void destroy_reqx(ReqX* x) {
+    if (!x) return;
+    if (x->ev_in) (void)hipEventDestroy(x->ev_in);
+    if (x->ev_out) (void)hipEventDestroy(x->ev_out);
+    delete x;
+}
+
+ReqX* rx(sched::Request* q) { return static_cast<ReqX*>(q->user); }
+
+// A step enqueued on the compute stream and not yet retired.
+struct InFlight {
+    std::vector<sched::StepItem> items;
+    hipEvent_t ea = nullptr, eb = nullptr;  // around the step's launches
 };
+
+constexpr int kMaxInFlight = 2;  // steps enqueued ahead of the device
 
 }  // namespace
 
@@ -126,195 +71,176 @@ struct tina_server_s {
     std::condition_variable cv_work, cv_done;
     std::thread th;
     bool stop = false;
-    bool failed = false;
-    std::string fail_msg;
 
-    std::deque<uint64_t> queue;
-    std::unordered_map<uint64_t, Req*> reqs;
-    std::vector<Req*> active, draining;
-    std::vector<LStream> streams;
+    std::unique_ptr<sched::Scheduler> sch;  // every access under mu
+    std::vector<tina_pfb_plan_s*> stream_plans;
+    std::vector<tina_pfb_state_s*> stream_states;
     std::map<std::string, tina_pfb_plan_s*> plans;
-    uint64_t next_id = 1;
+    std::vector<sched::Request*> draining;  // output copies in flight
 
-    Arena arena;
     uint8_t* arena_base = nullptr;
     tina_pfb_batch_s* batch = nullptr;
     hipStream_t s_comp = nullptr, s_h2d = nullptr, s_d2h = nullptr;  // copies in and out on their own streams
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    std::vector<hipEvent_t> ev_pool;  // timing events of retired steps, for reuse
+    std::deque<InFlight> inflight;    // loop thread only
     std::chrono::steady_clock::time_point t0;
-    tina_server_stats stats{};
+    double device_busy_ms = 0.0;
 
     double now_us() const {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     }
+    hipEvent_t take_event() {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
     void loop();
-    void finish(Req* q, int status);
+    bool retire(bool block);
+    // Streams of requests that failed continue from the residue the scheduler
+    // assumes (the whole request consumed); their history is not repaired.
+    void resync(const std::vector<sched::Request*>& ended) {
+        for (sched::Request* q : ended) stream_states[q->stream]->residue = sch->stream(q->stream).residue_issued;
+    }
+    void complete(const std::vector<sched::Request*>& done);
+    void finish(sched::Request* q, int status) {
+        sch->finish(q, status, now_us());
+        cv_done.notify_all();
+    }
 };
 
-namespace {
-
-void destroy_req(Req* q) {
-    if (q->ev_in) (void)hipEventDestroy(q->ev_in);
-    if (q->ev_out) (void)hipEventDestroy(q->ev_out);
-    delete q;
+// Requests whose samples have all been processed (lock held): device
+// buffers are done; host buffers copy their output rows back first.
+void tina_server_s::complete(const std::vector<sched::Request*>& done) {
+    for (sched::Request* q : done) {
+        ReqX* x = rx(q);
+        if (q->device) {
+            finish(q, TINA_OK);
+            continue;
+        }
+        if (q->frames_done > 0)
+            (void)hipMemcpyAsync(x->r.host_out, arena_base + q->off_out, q->frames_done * x->row_bytes,
+                                 hipMemcpyDeviceToHost, s_d2h);
+        (void)hipEventRecord(x->ev_out, s_d2h);
+        draining.push_back(q);
+    }
 }
 
-}  // namespace
-
-// Marks q done with `status` (lock held), frees its arena buffers.
-void tina_server_s::finish(Req* q, int status) {
-    if (q->off_in >= 0) arena.release(q->off_in);
-    if (q->off_out >= 0) arena.release(q->off_out);
-    q->off_in = q->off_out = -1;
-    q->res.status = status;
-    q->res.frames = q->frames_done;
-    q->res.t_done_us = now_us();
-    q->phase = DONE;
-    if (status == TINA_OK) ++stats.completed;
+// Retires the oldest in-flight step if it has completed (or, with block,
+// once it has): its timing, the progress of its requests, and the requests
+// it completed.  Returns whether a step was retired.
+bool tina_server_s::retire(bool block) {
+    if (inflight.empty()) return false;
+    InFlight& f = inflight.front();
+    hipError_t e = block ? hipEventSynchronize(f.eb) : hipEventQuery(f.eb);
+    if (e == hipErrorNotReady) return false;
+    float ms = 0.f;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, f.ea, f.eb);
+    std::unique_lock<std::mutex> lk(mu);
+    device_busy_ms += ms;
+    std::vector<sched::Request*> ended;
+    complete(sch->step_done(f.items, e == hipSuccess, TINA_ERR_DEVICE, now_us(), &ended));
+    for (sched::Request* q : ended) rx(q)->fail_msg = std::string("step failed on the device: ") + hipGetErrorString(e);
+    resync(ended);
+    ev_pool.push_back(f.ea);
+    ev_pool.push_back(f.eb);
+    inflight.pop_front();
     cv_done.notify_all();
+    return true;
 }
 
 void tina_server_s::loop() {
     (void)hipSetDevice(cfg.device);
-    std::vector<tina_pfb_work> items;
-    std::vector<Req*> in_step;
+    std::vector<tina_pfb_work> works;
     for (;;) {
-        std::vector<Req*> admitted;
+        std::vector<sched::Request*> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (stop && queue.empty() && active.empty() && draining.empty()) break;
-            // Admission in arrival order; a request of a busy stream waits, a
-            // request that does not fit the arena blocks the ones behind it.
-            for (auto it = queue.begin(); it != queue.end();) {
-                Req* q = reqs[*it];
-                LStream& ls = streams[q->r.stream_id];
-                if (ls.busy || ls.queued.empty() || ls.queued.front() != q->id) { ++it; continue; }
-                if ((int)active.size() >= cfg.max_active) break;
-                if (!(q->r.flags & TINA_REQ_DEVICE_BUFFERS)) {
-                    const int64_t oi = arena.alloc(q->in_bytes);
-                    const int64_t oo = oi >= 0 ? arena.alloc(q->out_bytes) : -1;
-                    if (oi < 0 || oo < 0) {
-                        if (oi >= 0) arena.release(oi);
-                        ++stats.admission_waits;
-                        break;
-                    }
-                    q->off_in = oi;
-                    q->off_out = oo;
-                }
-                q->phase = ACTIVE;
-                q->res.t_admit_us = now_us();
-                ls.busy = true;
-                ls.queued.erase(ls.queued.begin());
-                active.push_back(q);
-                admitted.push_back(q);
-                ++stats.admitted;
-                it = queue.erase(it);
-            }
-            stats.arena_in_use = arena.used();
-            stats.arena_high_water = arena.high();
+            if (stop && sch->queued() == 0 && sch->active().empty() && draining.empty() && inflight.empty()) break;
+            admitted = sch->admit(now_us());
         }
-        for (Req* q : admitted) {  // input copies, outside the lock
-            if (q->r.flags & TINA_REQ_DEVICE_BUFFERS) continue;  // ev_in was recorded at submit
-            if (q->in_bytes > 0 && q->r.n_samples > 0)
-                (void)hipMemcpyAsync(arena_base + q->off_in, q->r.host_in, q->r.n_samples * q->sample_bytes,
+        for (sched::Request* q : admitted) {  // input copies, outside the lock
+            ReqX* x = rx(q);
+            if (q->device) continue;  // ev_in was recorded at submit
+            if (q->in_bytes > 0 && q->n_samples > 0)
+                (void)hipMemcpyAsync(arena_base + q->off_in, x->r.host_in, q->n_samples * x->sample_bytes,
                                      hipMemcpyHostToDevice, s_h2d);
-            (void)hipEventRecord(q->ev_in, s_h2d);
+            (void)hipEventRecord(x->ev_in, s_h2d);
+        }
+        while (retire(false)) {
         }
 
-        // Build the step: every active request whose input is on the device.
-        // The workspace and the step graph's grid hold max_active requests of
-        // frames_per_step frames each; when fewer are ready, each may take
-        // proportionally more, so a lone long request does not crawl through
-        // many small steps.
-        items.clear();
-        in_step.clear();
-        std::vector<Req*> empty_done;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            int64_t n_ready = 0;
-            for (Req* q : active) {
-                if (!q->in_ready) q->in_ready = hipEventQuery(q->ev_in) == hipSuccess;
-                if (q->in_ready && q->r.n_samples > 0) ++n_ready;
+        // Build and enqueue the next step while up to kMaxInFlight - 1 others
+        // are still on the device: the host's step turnaround (table fill,
+        // launches) overlaps the device's work.
+        bool built = false;
+        if ((int)inflight.size() < kMaxInFlight) {
+            std::vector<sched::StepItem> items;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                for (sched::Request* q : sch->active())
+                    if (!q->in_ready) q->in_ready = hipEventQuery(rx(q)->ev_in) == hipSuccess;
+                (void)hipGetLastError();  // a pending event's query is not an error
+                complete(sch->take_empty());
+                items = sch->build_step(now_us());
             }
-            const int64_t quota = cfg.frames_per_step * std::max<int64_t>(1, cfg.max_active / std::max<int64_t>(1, n_ready));
-            for (Req* q : active) {
-                if (!q->in_ready) continue;
-                if (q->r.n_samples == 0) { empty_done.push_back(q); continue; }
-                LStream& ls = streams[q->r.stream_id];
-                const int64_t P = ls.plan->P;
-                const int64_t r = ls.state->residue;
-                const int64_t s = std::min(q->r.n_samples - q->samples_done, quota * P - r);
-                tina_pfb_work w{};
-                w.plan = ls.plan;
-                w.state = ls.state;
-                const bool dev = (q->r.flags & TINA_REQ_DEVICE_BUFFERS) != 0;
-                const uint8_t* in0 = dev ? (const uint8_t*)q->r.host_in : arena_base + q->off_in;
-                uint8_t* out0 = dev ? (uint8_t*)q->r.host_out : arena_base + q->off_out;
-                w.d_in = in0 + q->samples_done * q->sample_bytes;
-                w.n_samples = s;
-                w.d_out = out0 + q->frames_done * q->row_bytes;
-                w.out_capacity_frames = q->frames_total - q->frames_done;
-                items.push_back(w);
-                in_step.push_back(q);
-            }
-        }
-        if (!items.empty()) {
-            const double t_launch = now_us();
-            (void)hipEventRecord(ev_a, s_comp);
-            tina_status st = batch_run_items(batch, items.data(), (int32_t)items.size(), s_comp, cfg.use_graph != 0);
-            (void)hipEventRecord(ev_b, s_comp);
-            hipError_t e = hipEventSynchronize(ev_b);
-            float ms = 0.f;
-            if (e == hipSuccess) (void)hipEventElapsedTime(&ms, ev_a, ev_b);
-            std::unique_lock<std::mutex> lk(mu);
-            ++stats.steps;
-            stats.device_busy_ms += ms;
-            for (size_t i = 0; i < in_step.size(); ++i) {
-                Req* q = in_step[i];
-                if (q->res.steps == 0) q->res.t_first_step_us = t_launch;
-                ++q->res.steps;
-                if (st != TINA_OK || e != hipSuccess) continue;
-                q->samples_done += items[i].n_samples;
-                q->frames_done += items[i].frames_written;
-                stats.samples += items[i].n_samples;
-                stats.frames += items[i].frames_written;
-            }
-            if (st != TINA_OK || e != hipSuccess) {  // the step failed: fail its requests
-                for (Req* q : in_step) {
-                    streams[q->r.stream_id].busy = false;
-                    active.erase(std::find(active.begin(), active.end(), q));
-                    finish(q, st != TINA_OK ? st : TINA_ERR_DEVICE);
+            if (!items.empty()) {
+                works.clear();
+                for (const sched::StepItem& it : items) {
+                    ReqX* x = rx(it.q);
+                    const int s = it.q->stream;
+                    tina_pfb_work w{};
+                    w.plan = stream_plans[s];
+                    w.state = stream_states[s];
+                    const uint8_t* in0 = it.q->device ? (const uint8_t*)x->r.host_in : arena_base + it.q->off_in;
+                    uint8_t* out0 = it.q->device ? (uint8_t*)x->r.host_out : arena_base + it.q->off_out;
+                    w.d_in = in0 + it.sample0 * x->sample_bytes;
+                    w.n_samples = it.n_samples;
+                    w.d_out = out0 + it.frame0 * x->row_bytes;
+                    w.out_capacity_frames = it.q->frames_total - it.frame0;
+                    works.push_back(w);
                 }
-                cv_work.notify_all();
-                continue;
+                InFlight f;
+                f.items = std::move(items);
+                f.ea = take_event();
+                f.eb = take_event();
+                tina_status st = (f.ea && f.eb) ? TINA_OK : TINA_ERR_DEVICE;
+                if (st == TINA_OK && hipEventRecord(f.ea, s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+                if (st == TINA_OK)
+                    st = batch_run_items(batch, works.data(), (int32_t)works.size(), s_comp, cfg.use_graph != 0);
+                if (st == TINA_OK && hipEventRecord(f.eb, s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+                if (st != TINA_OK) {  // nothing of this step may run: fail its requests
+                    (void)hipStreamSynchronize(s_comp);
+                    const std::string msg = tina_last_error();
+                    std::unique_lock<std::mutex> lk(mu);
+                    std::vector<sched::Request*> ended;
+                    sch->step_done(f.items, false, st, now_us(), &ended);
+                    for (sched::Request* q : ended) rx(q)->fail_msg = "step launch failed: " + msg;
+                    resync(ended);
+                    for (hipEvent_t e : {f.ea, f.eb})
+                        if (e) ev_pool.push_back(e);
+                    cv_done.notify_all();
+                } else {
+                    inflight.push_back(std::move(f));
+                    built = true;
+                }
             }
         }
-        // Requests whose samples are all processed: copy their output back.
+        // Wait for the device when the pipeline is full, or when nothing new
+        // could be built and a step is still running.
+        if (!inflight.empty() && ((int)inflight.size() >= kMaxInFlight || !built)) retire(true);
         {
             std::unique_lock<std::mutex> lk(mu);
-            for (auto it = active.begin(); it != active.end();) {
-                Req* q = *it;
-                const bool empty = std::find(empty_done.begin(), empty_done.end(), q) != empty_done.end();
-                if (!empty && (q->samples_done < q->r.n_samples || !q->in_ready)) { ++it; continue; }
-                // Device buffers: the step that wrote the last rows has been
-                // waited for, so only host outputs need a copy.
-                if (q->frames_done > 0 && !(q->r.flags & TINA_REQ_DEVICE_BUFFERS))
-                    (void)hipMemcpyAsync(q->r.host_out, arena_base + q->off_out, q->frames_done * q->row_bytes,
-                                         hipMemcpyDeviceToHost, s_d2h);
-                (void)hipEventRecord(q->ev_out, s_d2h);
-                q->phase = DRAINING;
-                streams[q->r.stream_id].busy = false;
-                draining.push_back(q);
-                it = active.erase(it);
-            }
             for (auto it = draining.begin(); it != draining.end();) {
-                Req* q = *it;
-                if (hipEventQuery(q->ev_out) != hipSuccess) { ++it; continue; }
+                sched::Request* q = *it;
+                if (hipEventQuery(rx(q)->ev_out) != hipSuccess) { ++it; continue; }
                 finish(q, TINA_OK);
                 it = draining.erase(it);
             }
-            const bool idle = items.empty();
-            if (idle && !stop) cv_work.wait_for(lk, std::chrono::microseconds(100));
+            if (!built && inflight.empty() && !stop) cv_work.wait_for(lk, std::chrono::microseconds(100));
         }
     }
 }
@@ -341,18 +267,17 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     if (!sv) return fail(TINA_ERR_OUT_OF_MEMORY, "server_create: host allocation");
     sv->cfg = *c;
     sv->t0 = std::chrono::steady_clock::now();
+    sv->sch.reset(new (std::nothrow) sched::Scheduler(c->max_active, c->max_queued, c->frames_per_step, c->hbm_budget_bytes));
     auto bail = [&](tina_status st, const std::string& m) {
         if (sv->batch) tina_pfb_batch_destroy(sv->batch);
         if (sv->arena_base) (void)hipFree(sv->arena_base);
         for (hipStream_t s : {sv->s_comp, sv->s_h2d, sv->s_d2h})
             if (s) (void)hipStreamDestroy(s);
-        for (hipEvent_t e : {sv->ev_a, sv->ev_b})
-            if (e) (void)hipEventDestroy(e);
         delete sv;
         return fail(st, m);
     };
+    if (!sv->sch) return bail(TINA_ERR_OUT_OF_MEMORY, "server_create: host allocation");
     if (hipMalloc(&sv->arena_base, c->hbm_budget_bytes) != hipSuccess) return bail(TINA_ERR_OUT_OF_MEMORY, "server_create: arena");
-    sv->arena.init(c->hbm_budget_bytes);
     const int64_t ws = (int64_t)c->max_active * c->frames_per_step * 2 * c->max_channels * 4;
     tina_status st = tina_pfb_batch_create(c->device, c->precision, c->max_active, std::max<int64_t>(ws, 1 << 20), &sv->batch);
     if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
@@ -362,9 +287,13 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
                                          ((2 * (int64_t)c->max_channels + kGemmBN - 1) / kGemmBN));
     if (hipStreamCreateWithFlags(&sv->s_comp, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&sv->s_h2d, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&sv->s_d2h, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&sv->ev_a) != hipSuccess || hipEventCreate(&sv->ev_b) != hipSuccess)
-        return bail(TINA_ERR_DEVICE, "server_create: streams/events");
+        hipStreamCreateWithFlags(&sv->s_d2h, hipStreamNonBlocking) != hipSuccess)
+        return bail(TINA_ERR_DEVICE, "server_create: streams");
+    for (int i = 0; i < 2 * kMaxInFlight; ++i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return bail(TINA_ERR_DEVICE, "server_create: events");
+        sv->ev_pool.push_back(e);
+    }
     if (c->use_graph) {  // every step graph now, none while requests run
         st = batch_prepare_graphs(sv->batch, sv->s_comp);
         if (st == TINA_OK && hipStreamSynchronize(sv->s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
@@ -380,27 +309,25 @@ tina_status tina_server_destroy(tina_server_t sv) {
     {
         std::unique_lock<std::mutex> lk(sv->mu);
         sv->stop = true;
-        for (uint64_t id : sv->queue) {  // queued requests are cancelled
-            Req* q = sv->reqs[id];
-            q->res.status = TINA_ERR_CANCELLED;
-            q->phase = DONE;
-        }
-        sv->queue.clear();
+        sv->sch->cancel_all_queued(sv->now_us());  // queued requests are cancelled
         sv->cv_work.notify_all();
+        sv->cv_done.notify_all();
     }
     if (sv->th.joinable()) sv->th.join();
     DeviceScope ds(sv->cfg.device);
     (void)hipDeviceSynchronize();
-    for (auto& kv : sv->reqs) destroy_req(kv.second);
-    for (LStream& ls : sv->streams) tina_pfb_state_destroy(ls.state);
+    for (uint64_t id : sv->sch->ids()) {  // every request the scheduler still holds
+        destroy_reqx(rx(sv->sch->find(id)));
+        sv->sch->erase(id);
+    }
+    for (tina_pfb_state_s* st : sv->stream_states) tina_pfb_state_destroy(st);
     for (auto& kv : sv->plans) tina_pfb_plan_destroy(kv.second);
     tina_pfb_batch_destroy(sv->batch);
     (void)hipFree(sv->arena_base);
     (void)hipStreamDestroy(sv->s_comp);
     (void)hipStreamDestroy(sv->s_h2d);
     (void)hipStreamDestroy(sv->s_d2h);
-    (void)hipEventDestroy(sv->ev_a);
-    (void)hipEventDestroy(sv->ev_b);
+    for (hipEvent_t e : sv->ev_pool) (void)hipEventDestroy(e);
     delete sv;
     return TINA_OK;
 }
@@ -411,7 +338,7 @@ tina_status tina_server_stream_create(tina_server_t sv, int32_t P, int32_t M, in
     if (window == TINA_WINDOW_CUSTOM) return fail(TINA_ERR_INVALID_ARGUMENT, "stream_create: custom taps are not supported here");
     if (P > sv->cfg.max_channels) return fail(TINA_ERR_INVALID_ARGUMENT, "stream_create: channels above the server's max_channels");
     std::unique_lock<std::mutex> lk(sv->mu);
-    if ((int)sv->streams.size() >= sv->cfg.max_streams) return fail(TINA_ERR_BUSY, "stream_create: max_streams reached");
+    if (sv->sch->n_streams() >= sv->cfg.max_streams) return fail(TINA_ERR_BUSY, "stream_create: max_streams reached");
     const std::string key = std::to_string(P) + "/" + std::to_string(M) + "/" + std::to_string(sample_type) + "/" +
                             std::to_string(window);
     tina_pfb_plan_s* plan = nullptr;
@@ -433,12 +360,12 @@ tina_status tina_server_stream_create(tina_server_t sv, int32_t P, int32_t M, in
         if (st != TINA_OK) return st;
         sv->plans[key] = plan;
     }
-    LStream ls;
-    ls.plan = plan;
-    tina_status st = tina_pfb_state_create(plan, &ls.state);
+    tina_pfb_state_s* state = nullptr;
+    tina_status st = tina_pfb_state_create(plan, &state);
     if (st != TINA_OK) return st;
-    sv->streams.push_back(ls);
-    *stream_id = (int32_t)sv->streams.size() - 1;
+    sv->stream_plans.push_back(plan);
+    sv->stream_states.push_back(state);
+    *stream_id = sv->sch->add_stream(P);
     return TINA_OK;
 }
 
@@ -447,63 +374,69 @@ tina_status tina_pfb_submit(tina_server_t sv, const tina_request* r, uint64_t* i
     const double t = sv->now_us();
     std::unique_lock<std::mutex> lk(sv->mu);
     if (sv->stop) return fail(TINA_ERR_CANCELLED, "submit: server is stopping");
-    if (r->stream_id < 0 || r->stream_id >= (int)sv->streams.size()) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad stream id");
+    if (r->stream_id < 0 || r->stream_id >= sv->sch->n_streams()) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad stream id");
     if (r->n_samples < 0 || (r->n_samples > 0 && !r->host_in)) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad input");
     if (r->flags & ~TINA_REQ_DEVICE_BUFFERS) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: unknown flags");
     const bool dev = (r->flags & TINA_REQ_DEVICE_BUFFERS) != 0;
     if (dev && (((uintptr_t)r->host_in & 3) || ((uintptr_t)r->host_out & 7)))
         return fail(TINA_ERR_INVALID_ARGUMENT, "submit: device buffers misaligned");
-    LStream& ls = sv->streams[r->stream_id];
-    const tina_pfb_plan_s* p = ls.plan;
-    const int64_t frames = (ls.submitted_residue + r->n_samples) / p->P;
+    const tina_pfb_plan_s* p = sv->stream_plans[r->stream_id];
+    const int64_t frames = sv->sch->frames_if_submitted(r->stream_id, r->n_samples);
     if (frames > 0 && !r->host_out) return fail(TINA_ERR_INVALID_ARGUMENT, "submit: NULL output");
     if (frames > r->out_capacity_frames)
         return fail(TINA_ERR_INVALID_ARGUMENT, "submit: output capacity below the " + std::to_string(frames) + " frames of this request");
-    Req* q = new (std::nothrow) Req();
-    if (!q) return fail(TINA_ERR_OUT_OF_MEMORY, "submit: host allocation");
-    q->r = *r;
-    q->sample_bytes = p->cf * 4;
-    q->row_bytes = p->kout * 8;
-    q->frames_total = frames;
-    q->in_bytes = dev ? 0 : r->n_samples * q->sample_bytes;  // arena bytes (none for device buffers)
-    q->out_bytes = dev ? 0 : frames * q->row_bytes;
-    if (Arena::round(q->in_bytes) + Arena::round(q->out_bytes) > sv->arena.capacity()) {
-        delete q;
-        return fail(TINA_ERR_TOO_LARGE, "submit: request buffers exceed the HBM budget");
-    }
-    if ((int)sv->queue.size() >= sv->cfg.max_queued) {
-        delete q;
-        return fail(TINA_ERR_BUSY, "submit: queue full");
-    }
-    if (hipEventCreateWithFlags(&q->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&q->ev_out, hipEventDisableTiming) != hipSuccess) {
-        destroy_req(q);
+    ReqX* x = new (std::nothrow) ReqX();
+    if (!x) return fail(TINA_ERR_OUT_OF_MEMORY, "submit: host allocation");
+    x->r = *r;
+    x->sample_bytes = p->cf * 4;
+    x->row_bytes = p->kout * 8;
+    if (hipEventCreateWithFlags(&x->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&x->ev_out, hipEventDisableTiming) != hipSuccess) {
+        destroy_reqx(x);
         return fail(TINA_ERR_DEVICE, "submit: events");
     }
-    if (dev && hipEventRecord(q->ev_in, (hipStream_t)r->ready_stream) != hipSuccess) {
-        destroy_req(q);
+    if (dev && hipEventRecord(x->ev_in, (hipStream_t)r->ready_stream) != hipSuccess) {
+        destroy_reqx(x);
         return fail(TINA_ERR_DEVICE, "submit: recording the input-ready event on ready_stream");
     }
-    q->id = sv->next_id++;
-    q->res.t_submit_us = t;
-    ls.submitted_residue = (ls.submitted_residue + r->n_samples) % p->P;
-    ls.queued.push_back(q->id);
-    sv->reqs[q->id] = q;
-    sv->queue.push_back(q->id);
+    sched::Request* q = nullptr;
+    switch (sv->sch->submit(r->stream_id, r->n_samples, dev, x->sample_bytes, x->row_bytes, t, &q)) {
+        case sched::SUBMIT_OK: break;
+        case sched::SUBMIT_TOO_LARGE:
+            destroy_reqx(x);
+            return fail(TINA_ERR_TOO_LARGE, "submit: request buffers exceed the HBM budget");
+        case sched::SUBMIT_BUSY:
+            destroy_reqx(x);
+            return fail(TINA_ERR_BUSY, "submit: queue full");
+        default:
+            destroy_reqx(x);
+            return fail(TINA_ERR_INVALID_ARGUMENT, "submit: bad stream id");
+    }
+    q->user = x;
     *id = q->id;
     sv->cv_work.notify_all();
     return TINA_OK;
 }
 
 static tina_status take_result(tina_server_s* sv, uint64_t id, tina_result* res, bool& ready) {
-    auto it = sv->reqs.find(id);
-    if (it == sv->reqs.end()) return fail(TINA_ERR_INVALID_ARGUMENT, "unknown request id");
-    Req* q = it->second;
-    ready = q->phase == DONE;
+    sched::Request* q = sv->sch->find(id);
+    if (!q) return fail(TINA_ERR_INVALID_ARGUMENT, "unknown request id");
+    ready = q->phase == sched::DONE;
     if (!ready) return TINA_ERR_NOT_READY;
-    if (res) *res = q->res;
-    sv->reqs.erase(it);
-    destroy_req(q);
+    if (res) {
+        *res = tina_result{};
+        res->status = q->status < 0 ? TINA_ERR_CANCELLED : q->status;
+        res->frames = q->frames_done;
+        res->t_submit_us = q->t_submit;
+        res->t_admit_us = q->t_admit;
+        res->t_first_step_us = q->t_first_step;
+        res->t_done_us = q->t_done;
+        res->steps = q->steps;
+    }
+    // A failed request's reason becomes the caller's tina_last_error().
+    if (q->status > 0 && !rx(q)->fail_msg.empty()) (void)fail(TINA_OK, "request failed: " + rx(q)->fail_msg);
+    destroy_reqx(rx(q));
+    sv->sch->erase(id);
     return TINA_OK;
 }
 
@@ -533,19 +466,10 @@ tina_status tina_pfb_wait(tina_server_t sv, uint64_t id, int64_t timeout_us, tin
 tina_status tina_pfb_cancel(tina_server_t sv, uint64_t id) {
     if (!sv) return fail(TINA_ERR_INVALID_ARGUMENT, "cancel: NULL server");
     std::unique_lock<std::mutex> lk(sv->mu);
-    auto it = sv->reqs.find(id);
-    if (it == sv->reqs.end()) return fail(TINA_ERR_INVALID_ARGUMENT, "cancel: unknown request id");
-    Req* q = it->second;
-    if (q->phase != QUEUED) return TINA_ERR_NOT_READY;
-    LStream& ls = sv->streams[q->r.stream_id];
-    if (ls.queued.empty() || ls.queued.back() != id)
-        return fail(TINA_ERR_INVALID_ARGUMENT, "cancel: only the newest queued request of a stream can be cancelled");
-    ls.queued.pop_back();
-    ls.submitted_residue = ((ls.submitted_residue - q->r.n_samples) % ls.plan->P + ls.plan->P) % ls.plan->P;
-    sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), id));
-    q->res.status = TINA_ERR_CANCELLED;
-    q->res.t_done_us = sv->now_us();
-    q->phase = DONE;
+    if (!sv->sch->find(id)) return fail(TINA_ERR_INVALID_ARGUMENT, "cancel: unknown request id");
+    const int c = sv->sch->cancel(id, sv->now_us());
+    if (c == 0) return TINA_ERR_NOT_READY;
+    if (c < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "cancel: only the newest queued request of a stream can be cancelled");
     sv->cv_done.notify_all();
     return TINA_OK;
 }
@@ -553,10 +477,18 @@ tina_status tina_pfb_cancel(tina_server_t sv, uint64_t id) {
 tina_status tina_server_get_stats(tina_server_t sv, tina_server_stats* s) {
     if (!sv || !s) return fail(TINA_ERR_INVALID_ARGUMENT, "stats: NULL argument");
     std::unique_lock<std::mutex> lk(sv->mu);
-    *s = sv->stats;
+    const sched::Stats& t = sv->sch->stats();
+    *s = tina_server_stats{};
+    s->steps = t.steps;
+    s->samples = t.samples;
+    s->frames = t.frames;
+    s->completed = t.completed;
+    s->admitted = t.admitted;
+    s->admission_waits = t.admission_waits;
+    s->device_busy_ms = sv->device_busy_ms;
     s->now_us = sv->now_us();
-    s->arena_in_use = sv->arena.used();
-    s->arena_high_water = sv->arena.high();
+    s->arena_in_use = sv->sch->arena().used();
+    s->arena_high_water = sv->sch->arena().high();
     return TINA_OK;
 }
 
@@ -566,7 +498,7 @@ tina_status tina_server_get_stats(tina_server_t sv, tina_server_stats* s) {
 tina_status tina_server_arena_simulate(int64_t capacity, const int64_t* ops, int32_t n, int64_t* out,
                                        int64_t* final_used) {
     if (!ops || !out || n < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "arena_simulate: NULL argument");
-    Arena a;
+    sched::Arena a;
     a.init(capacity);
     for (int i = 0; i < n; ++i) {
         if (ops[i] > 0) out[i] = a.alloc(ops[i]);
@@ -576,6 +508,99 @@ tina_status tina_server_arena_simulate(int64_t capacity, const int64_t* ops, int
         }
     }
     if (final_used) *final_used = a.used();
+    return TINA_OK;
+}
+
+// Host-only run of the scheduler on a scripted sequence of operations (see
+// tina_pfb_server.h): the same admission, quota, cancellation and
+// completion decisions as the server, with steps that complete or fail when
+// the script says so.
+tina_status tina_server_schedule_simulate(int32_t max_active, int32_t max_queued, int64_t frames_per_step,
+                                          int64_t arena_bytes, const tina_sched_op* ops, int32_t n_ops,
+                                          tina_sched_event* events, int32_t capacity, int32_t* n_events) {
+    if ((n_ops > 0 && !ops) || n_ops < 0 || !events || capacity < 0 || !n_events)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "schedule_simulate: NULL argument");
+    if (max_active < 1 || max_queued < 1 || frames_per_step < 1 || arena_bytes < 0)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "schedule_simulate: bad configuration");
+    sched::Scheduler sch(max_active, max_queued, frames_per_step, arena_bytes);
+    std::deque<std::vector<sched::StepItem>> inflight;
+    int32_t ne = 0;
+    double t = 0.0;
+    auto emit = [&](int32_t kind, int32_t status, uint64_t id, int64_t a, int64_t b) {
+        if (ne < capacity) events[ne] = tina_sched_event{kind, status, id, a, b};
+        ++ne;
+    };
+    auto done = [&](const std::vector<sched::Request*>& qs, int status) {
+        for (sched::Request* q : qs) {
+            if (q->phase != sched::DONE) sch.finish(q, status, t);
+            emit(TINA_SCHED_COMPLETE, status, q->id, q->frames_done, q->steps);
+        }
+    };
+    for (int32_t i = 0; i < n_ops; ++i, t += 1.0) {
+        const tina_sched_op& op = ops[i];
+        switch (op.kind) {
+            case TINA_SCHED_ADD_STREAM:
+                if (op.arg < 1) return fail(TINA_ERR_INVALID_ARGUMENT, "schedule_simulate: channels must be >= 1");
+                emit(TINA_SCHED_ADD_STREAM, TINA_OK, (uint64_t)sch.add_stream(op.arg), op.arg, 0);
+                break;
+            case TINA_SCHED_SUBMIT: {
+                const bool dev = op.value < 0;
+                const int64_t n = dev ? -op.value : op.value;
+                sched::Request* q = nullptr;
+                const int P = op.arg >= 0 && op.arg < sch.n_streams() ? sch.stream(op.arg).P : 1;
+                const sched::SubmitResult r = sch.submit(op.arg, n, dev, 8, 8 * (int64_t)P, t, &q);
+                const int st = r == sched::SUBMIT_OK ? TINA_OK
+                             : r == sched::SUBMIT_TOO_LARGE ? TINA_ERR_TOO_LARGE
+                             : r == sched::SUBMIT_BUSY ? TINA_ERR_BUSY : TINA_ERR_INVALID_ARGUMENT;
+                emit(TINA_SCHED_SUBMIT, st, q ? q->id : 0, n, q ? q->frames_total : 0);
+                break;
+            }
+            case TINA_SCHED_ADMIT:
+                for (sched::Request* q : sch.admit(t)) {
+                    if (q->device) q->in_ready = true;  // device input: ready on admission
+                    emit(TINA_SCHED_ADMIT, TINA_OK, q->id, q->off_in, q->off_out);
+                }
+                break;
+            case TINA_SCHED_READY: {
+                sched::Request* q = sch.find((uint64_t)op.value);
+                if (q && q->phase == sched::ACTIVE) q->in_ready = true;
+                emit(TINA_SCHED_READY, q && q->phase == sched::ACTIVE ? TINA_OK : TINA_ERR_INVALID_ARGUMENT,
+                     (uint64_t)op.value, 0, 0);
+                break;
+            }
+            case TINA_SCHED_STEP: {
+                done(sch.take_empty(), TINA_OK);
+                std::vector<sched::StepItem> items = sch.build_step(t);
+                for (const sched::StepItem& it : items) emit(TINA_SCHED_STEP, TINA_OK, it.id, it.n_samples, it.frames);
+                emit(TINA_SCHED_STEP, TINA_OK, 0, (int64_t)items.size(), (int64_t)inflight.size() + (items.empty() ? 0 : 1));
+                if (!items.empty()) inflight.push_back(std::move(items));
+                break;
+            }
+            case TINA_SCHED_COMPLETE: {
+                if (inflight.empty()) {
+                    emit(TINA_SCHED_COMPLETE, TINA_ERR_INVALID_ARGUMENT, 0, 0, 0);
+                    break;
+                }
+                std::vector<sched::Request*> ended;
+                const bool ok = op.arg == TINA_OK;
+                std::vector<sched::Request*> complete = sch.step_done(inflight.front(), ok, op.arg, t, &ended);
+                inflight.pop_front();
+                done(complete, TINA_OK);
+                done(ended, op.arg);
+                break;
+            }
+            case TINA_SCHED_CANCEL: {
+                const int c = sch.cancel((uint64_t)op.value, t);
+                emit(TINA_SCHED_CANCEL, c > 0 ? TINA_OK : c == 0 ? TINA_ERR_NOT_READY : TINA_ERR_INVALID_ARGUMENT,
+                     (uint64_t)op.value, 0, 0);
+                break;
+            }
+            default:
+                return fail(TINA_ERR_INVALID_ARGUMENT, "schedule_simulate: unknown operation kind " + std::to_string(op.kind));
+        }
+    }
+    *n_events = ne;
+    if (ne > capacity) return fail(TINA_ERR_TOO_LARGE, "schedule_simulate: more events than capacity");
     return TINA_OK;
 }
 

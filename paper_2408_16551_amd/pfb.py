@@ -34,6 +34,7 @@ EXPORTS = [
     "tina_pfb_batch_split_units",
     "tina_server_create", "tina_server_destroy", "tina_server_stream_create", "tina_pfb_submit", "tina_pfb_poll",
     "tina_pfb_wait", "tina_pfb_cancel", "tina_server_get_stats", "tina_server_arena_simulate",
+    "tina_server_schedule_simulate",
     "tina_unfold", "tina_fir_create", "tina_fir_destroy", "tina_fir_execute",
 ]
 
@@ -75,6 +76,19 @@ class _ServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("admitted", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
                 ("device_busy_ms", ctypes.c_double), ("now_us", ctypes.c_double),
                 ("arena_in_use", ctypes.c_int64), ("arena_high_water", ctypes.c_int64)]
+
+
+class _SchedOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("arg", ctypes.c_int32), ("value", ctypes.c_int64)]
+
+
+class _SchedEvent(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("id", ctypes.c_uint64),
+                ("a", ctypes.c_int64), ("b", ctypes.c_int64)]
+
+
+SCHED = {"add_stream": 1, "submit": 2, "admit": 3, "ready": 4, "step": 5, "complete": 6, "cancel": 7}
+SCHED_NAME = {v: k for k, v in SCHED.items()}
 
 
 class _Desc(ctypes.Structure):
@@ -129,6 +143,8 @@ def load(path: str = LIB_PATH):
         "tina_pfb_cancel": ([vp, ctypes.c_uint64], i32),
         "tina_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
         "tina_server_arena_simulate": ([i64, vp, i32, vp, P64], i32),
+        "tina_server_schedule_simulate": ([i32, i32, i64, i64, ctypes.POINTER(_SchedOp), i32,
+                                           ctypes.POINTER(_SchedEvent), i32, ctypes.POINTER(ctypes.c_int32)], i32),
         "tina_unfold": ([vp, i64, i64, i64, vp, i64, P64, vp], i32),
         "tina_fir_create": ([i32, vp, i32, i32, ctypes.POINTER(vp)], i32),
         "tina_fir_destroy": ([vp], i32),
@@ -589,3 +605,18 @@ class Fir:
         check(load().tina_fir_execute(self.handle, ctypes.c_void_p(x.data_ptr() if x.numel() else 0), x.numel(),
                                       ctypes.c_void_p(out.data_ptr() if out.numel() else 0), _stream_handle(stream)))
         return out
+
+
+def schedule_simulate(ops, max_active=4, max_queued=64, frames_per_step=16, arena_bytes=1 << 30, capacity=4096):
+    """Run the server's scheduler on the host (tina_server_schedule_simulate).
+    ops: (kind, arg, value) tuples, kind a key of SCHED.  Returns the events
+    as dicts {kind, status, id, a, b}."""
+    arr = (_SchedOp * max(1, len(ops)))()
+    for i, (k, arg, val) in enumerate(ops):
+        arr[i].kind, arr[i].arg, arr[i].value = SCHED[k], int(arg), int(val)
+    ev = (_SchedEvent * capacity)()
+    n = ctypes.c_int32()
+    check(load().tina_server_schedule_simulate(int(max_active), int(max_queued), int(frames_per_step),
+                                               int(arena_bytes), arr, len(ops), ev, capacity, ctypes.byref(n)))
+    return [{"kind": SCHED_NAME[ev[i].kind], "status": ev[i].status, "id": ev[i].id, "a": ev[i].a, "b": ev[i].b}
+            for i in range(n.value)]
