@@ -206,9 +206,15 @@ tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vect
 // Fills the host table for items [g.first, g.first + g.count) and returns the
 // launch parameters.  `dry` leaves state updates out (tuning runs).
 void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, const GroupPlan& g,
-                const Tune& tune, bool dry, int& max_m, bool& all_exact) {
+                const Tune& tune, bool dry, int& max_m, bool& all_exact, bool& wide) {
     BatchTable* t = b->h_table;
     t->n_items = g.count;
+    // Reduced forms take the single-stream path's wide tiles when every item's
+    // K is a whole number of their K tiles (else all take 128 x 128 tiles).
+    int wbm = kGemmBM, wbn = tune.gemm_tile_n;
+    wide = form_fir_qmode(b->form) != 0;
+    for (int i = 0; i < g.count && wide; ++i) wide = gemm_batch_wide_tile(b->form, w[g.first + i].plan->K, wbm, wbn);
+    const int tile_m = wide ? wbm : kGemmBM, tile_n = wide ? wbn : tune.gemm_tile_n;
     max_m = 1;
     for (int i = 0; i < g.count; ++i) max_m = std::max(max_m, w[g.first + i].plan->M);
     const int MT = pow2_at_least(max_m);
@@ -285,7 +291,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         const int64_t runs = (F + TF - 1) / TF;
         fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
         fc[i] = (double)TF * ring;
-        gu[i] = F > 0 ? ((F + kGemmBM - 1) / kGemmBM) * ((p->N + tune.gemm_tile_n - 1) / tune.gemm_tile_n) : 0;
+        gu[i] = F > 0 ? ((F + tile_m - 1) / tile_m) * ((p->N + tile_n - 1) / tile_n) : 0;
         gc[i] = (double)p->K;
         bi.fir_unit0 = f0;
         bi.gemm_unit0 = g0;
@@ -303,7 +309,8 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         }
         s0 += su[i];
     }
-    t->gemm_bn = tune.gemm_tile_n;
+    t->gemm_bn = tile_n;
+    t->gemm_wide = wide ? 1 : 0;
     t->fir_units = f0;
     t->gemm_units = g0;
     t->st_units = s0;
@@ -343,14 +350,14 @@ int64_t gemm_grid(const BatchTable* t) {
 }
 
 tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
-                          bool always, int64_t fixed_gemm_grid = 0) {
+                          bool wide, bool always, int64_t fixed_gemm_grid = 0) {
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     const int qmode = form_fir_qmode(b->form);
     if (always || b->h_table->fir_units > 0)
         HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, qmode, grid_fir, s));
     if (always || b->h_table->gemm_units > 0)
-        HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s));
+        HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s, wide));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }
@@ -359,15 +366,15 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
 // launch shape), captured and instantiated on first use.  The GEMM launch is
 // found among the graph's kernel nodes by its grid (graph_gemm_grid is kept
 // apart from the fixed grids of the other stages).
-tina_status step_graph(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact,
+tina_status step_graph(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int max_m, bool all_exact, bool wide,
                        tina_pfb_batch_s::StepGraph*& out) {
-    const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + ":" +
-                            std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
+    const std::string key = std::to_string(pow2_at_least(max_m)) + (all_exact ? "e" : "p") + (wide ? "w" : "n") +
+                            ":" + std::to_string(tune.fir_tf_mult) + ":" + std::to_string(tune.gemm_tile_n);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        tina_status st = launch_stages(b, s, tune, max_m, all_exact, true, b->graph_gemm_grid);
+        tina_status st = launch_stages(b, s, tune, max_m, all_exact, wide, true, b->graph_gemm_grid);
         hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (st != TINA_OK || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -416,14 +423,14 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
         }
         b->h_table = b->h_tables[k];
         int max_m = 1;
-        bool all_exact = true;
-        fill_table(b, w, frames, g, tune, dry, max_m, all_exact);
+        bool all_exact = true, wide = false;
+        fill_table(b, w, frames, g, tune, dry, max_m, all_exact, wide);
         HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
         HIP_TRY(hipEventRecord(b->table_free[k], s));
         b->table_pending[k] = true;
         tina_pfb_batch_s::StepGraph* sg = nullptr;
         if (use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid) {
-            tina_status st = step_graph(b, s, tune, max_m, all_exact, sg);
+            tina_status st = step_graph(b, s, tune, max_m, all_exact, wide, sg);
             if (st != TINA_OK) return st;
             if (sg->gemm_node) {  // this step's GEMM grid: blocks past the tiles' ranges would only return
                 hipKernelNodeParams kp = sg->gemm_params;
@@ -445,7 +452,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
             // at once), so one graph per kernel variant serves every step.
             HIP_TRY(hipGraphLaunch(sg->exec, s));
         } else {
-            tina_status st = launch_stages(b, s, tune, max_m, all_exact, false);
+            tina_status st = launch_stages(b, s, tune, max_m, all_exact, wide, false);
             if (st != TINA_OK) return st;
         }
         if (!dry) {
@@ -516,12 +523,14 @@ tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hi
 tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s) {
     DeviceScope ds(b->device);
     const Tune tune;
+    const int n_wide = form_fir_qmode(b->form) != 0 ? 2 : 1;  // reduced forms: wide and 128 x 128 GEMM tiles
     for (int mt = 1; mt <= 64; mt *= 2)
-        for (int exact = 1; exact >= (mt == 1 ? 1 : 0); --exact) {
-            tina_pfb_batch_s::StepGraph* sg = nullptr;
-            tina_status st = step_graph(b, s, tune, mt, exact != 0, sg);
-            if (st != TINA_OK) return st;
-        }
+        for (int exact = 1; exact >= (mt == 1 ? 1 : 0); --exact)
+            for (int wide = 0; wide < n_wide; ++wide) {
+                tina_pfb_batch_s::StepGraph* sg = nullptr;
+                tina_status st = step_graph(b, s, tune, mt, exact != 0, wide != 0, sg);
+                if (st != TINA_OK) return st;
+            }
     return TINA_OK;
 }
 

@@ -1110,6 +1110,28 @@ __global__ __launch_bounds__(NT) void dft_gemm_batch_kernel(const BatchTable* __
     else gemm_tile<FORM, WN>(g, m0, n0, sm);
 }
 
+// Batched GEMM on the wide tiles: block b serves tile b / 8 of XCD b % 8's
+// range, as dft_gemm_batch_kernel, each item's tiles mapped as the
+// single-stream wide kernel maps them (same tiles, same bits).
+template <int FORM>
+__global__ __launch_bounds__(WideGeom<FORM>::NTH) __attribute__((amdgpu_waves_per_eu(2)))
+void dft_gemm_batch_wide_kernel(const BatchTable* __restrict__ t) {
+    using G = WideGeom<FORM>;
+    __shared__ __attribute__((aligned(16))) WideSmem<FORM> sm;
+    const int x = blockIdx.x & 7;
+    const int64_t u = t->gemm_bounds[x] + (blockIdx.x >> 3);
+    if (u >= t->gemm_bounds[x + 1]) return;
+    const int it = batch_find(t->items, t->n_items, u, /*stage=*/1);
+    const GemmArgs g = t->items[it].gemm;  // a private copy: read through the table, fields would be reloaded
+    const int64_t nm = (g.F + G::BM - 1) / G::BM, nn = (g.N + G::BN - 1) / G::BN;
+    const int64_t L = u - t->items[it].gemm_unit0;
+    const int64_t gsz_full = WIDE_GROUP_M * nn;
+    const int64_t grp = L / gsz_full, first_m = grp * WIDE_GROUP_M;
+    const int64_t gsz = min((int64_t)WIDE_GROUP_M, nm - first_m);
+    const int64_t within = L - grp * gsz_full;
+    gemm_tile_wide<FORM>(g, (first_m + within % gsz) * G::BM, (within / gsz) * G::BN, sm);
+}
+
 // Columns per wave: 4 MFMA blocks (128 x 256 tiles) for FP32, whose long
 // K tiles hide latency at 2 blocks per CU and whose tile count then fills the
 // chip in whole rounds; 2 (128 x 128) for the others.
@@ -1143,7 +1165,44 @@ hipError_t launch_raw(const GemmArgs& g, hipStream_t s) {
 
 bool gemm_raw_form(int form) { return form != FORM_FP32; }
 
-hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s) {
+bool gemm_batch_wide_tile(int form, int K, int& bm, int& bn) {
+    auto geom = [&](auto tag) {
+        using G = WideGeom<decltype(tag)::value>;
+        bm = G::BM;
+        bn = G::BN;
+        return K % G::BK == 0 && (int64_t)G::BM * K * FT<decltype(tag)::value>::EB < (1ll << 31) &&
+               (int64_t)G::BN * K * FT<decltype(tag)::value>::EB < (1ll << 31);
+    };
+    switch (form) {
+        case FORM_BF16: return geom(std::integral_constant<int, FORM_BF16>{});
+        case FORM_BF16X3: return geom(std::integral_constant<int, FORM_BF16X3>{});
+        case FORM_FP16: return geom(std::integral_constant<int, FORM_FP16>{});
+        case FORM_FP16X3: return geom(std::integral_constant<int, FORM_FP16X3>{});
+        case FORM_FP8: return geom(std::integral_constant<int, FORM_FP8>{});
+        case FORM_MXFP8: return geom(std::integral_constant<int, FORM_MXFP8>{});
+        default: return false;
+    }
+}
+
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s,
+                             bool wide) {
+    if (wide) {
+        if (!raw) return hipErrorInvalidValue;
+        auto go = [&](auto tag) {
+            constexpr int F = decltype(tag)::value;
+            hipLaunchKernelGGL((dft_gemm_batch_wide_kernel<F>), dim3(grid), dim3(WideGeom<F>::NTH), 0, s, t);
+            return hipGetLastError();
+        };
+        switch (form) {
+            case FORM_BF16: return go(std::integral_constant<int, FORM_BF16>{});
+            case FORM_BF16X3: return go(std::integral_constant<int, FORM_BF16X3>{});
+            case FORM_FP16: return go(std::integral_constant<int, FORM_FP16>{});
+            case FORM_FP16X3: return go(std::integral_constant<int, FORM_FP16X3>{});
+            case FORM_FP8: return go(std::integral_constant<int, FORM_FP8>{});
+            case FORM_MXFP8: return go(std::integral_constant<int, FORM_MXFP8>{});
+            default: return hipErrorInvalidValue;
+        }
+    }
     const dim3 gd(grid), bd(NT);
     if (tile_n == 2 * kGemmBN) {
         if (raw || form != FORM_FP32) return hipErrorInvalidValue;

@@ -153,8 +153,8 @@ struct BatchTable {
     int32_t pad_;
     int64_t fir_units, gemm_units, st_units;
     int64_t fir_bounds[9], gemm_bounds[9], st_bounds[9];
-    int32_t gemm_bn;        // GEMM tile columns of this launch (kGemmBN or 2 * kGemmBN)
-    int32_t pad2_;
+    int32_t gemm_bn;        // GEMM tile columns of this launch (kGemmBN or 2 * kGemmBN, or the wide tile's)
+    int32_t gemm_wide;      // the launch uses the wide raw-operand tiles
     BatchItem items[1];     // n_items entries follow
 };
 
@@ -205,7 +205,13 @@ __device__ inline int frame_exponent(float amax, float limit) {
 }
 // tile_n: the table's GEMM tile columns (kGemmBN for every form; 2 * kGemmBN
 // also for FP32 with A in FP32).
-hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s);
+// wide: A in operand form on the single-stream path's wide tiles (every
+// item's K a whole number of their K tiles; gemm_batch_wide_tile).
+hipError_t launch_gemm_batch(const BatchTable* t, int form, bool raw, int tile_n, int grid, hipStream_t s,
+                             bool wide = false);
+// The wide raw-operand tile (bm x bn) of `form`, if it serves an operand of K
+// columns (K a whole number of its K tiles); false for FP32 and other K.
+bool gemm_batch_wide_tile(int form, int K, int& bm, int& bn);
 hipError_t launch_gather_batch(const BatchTable* t, int grid, hipStream_t s);
 
 }  // namespace tina
