@@ -300,10 +300,33 @@ def ops_bench(torch, steps=10):
     return res
 
 
-def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
+def sampled_check(oracle_obj, cases, seed, n_frames=64):
+    """rel-L2 vs the FP64 oracle over sampled frames of several streams:
+    cases = [(x, P, M, got)], x the whole input of a stream (zero history),
+    got its frames x P output (numpy).  The error is pooled over the cases
+    (one norm over all sampled frames); the worst single case beside it."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    num = den = 0.0
+    worst = 0.0
+    for x, P, M, got in cases:
+        F = got.shape[0]
+        fr = np.unique(np.concatenate([np.arange(min(F, M + 1)), [F - 1],
+                                       g.choice(F, size=min(F, n_frames), replace=False)])).astype(np.int64)
+        ref = oracle_obj.pfb(x, P, M, oracle_obj.window(P, M, "hann"), frames=fr)
+        d = float(np.linalg.norm(got[fr].astype(np.complex128) - ref) ** 2)
+        r = float(np.linalg.norm(ref) ** 2)
+        num, den = num + d, den + r
+        worst = max(worst, (d / r) ** 0.5)
+    return {"rel_l2_vs_fp64_oracle": float(f"{(num / den) ** 0.5:.3e}"),
+            "worst_stream_rel_l2": float(f"{worst:.3e}"), "streams_checked": len(cases),
+            "frames_per_stream": f"first M+1, last, {n_frames} random"}
+
+
+def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5, oracle_obj=None):
     """The ragged batch: 64 complex64 streams, log-uniform lengths 2^18-2^22,
     channels from {256, 512, 1024}, 16 taps, one persistent launch per stage,
-    autotuned launch shapes."""
+    autotuned launch shapes.  With an oracle: 4 seeded items of the timed
+    batch are checked on sampled frames."""
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Batch, Plan
     specs, xs = workloads.ragged_batch()
@@ -329,6 +352,10 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
         res[prec] = {"gsps": round(total / sec / 1e9, 3), "ms_per_batch": round(sec * 1e3, 3),
                      "dft_useful_tflops_incl_fir": round(flops / sec / 1e12, 2),
                      "tuned": {"fir_frames_per_thread_mult": tf, "gemm_tile_n": tile_n}}
+        if oracle_obj is not None:
+            pick = np.random.Generator(np.random.PCG64(77)).choice(len(items), size=4, replace=False)
+            res[prec]["check"] = sampled_check(
+                oracle_obj, [(xs[i], specs[i].P, 16, outs[i].cpu().numpy()) for i in sorted(pick)], seed=78)
         log(f"[bench] batched {prec}: {res[prec]}")
         b.close()
         del outs, items
@@ -338,13 +365,15 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5):
 _BATCHED_CAPACITY = {}
 
 
-def serving_mix_batched_capacity(torch, precision, seed=1005, reps=5):
+def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5):
     """Capacity C of the batched path on the serving mix: one request of
     log-uniform length 2^16-2^22 on each of the 64 logical streams, run as one
     tina_pfb_batch_execute (every item with its stream's plan and state),
-    closed loop, inputs and outputs in HBM.  GSamples/s."""
-    if precision in _BATCHED_CAPACITY:
-        return _BATCHED_CAPACITY[precision]
+    closed loop, inputs and outputs in HBM.  host=True: end to end from pinned
+    host buffers (each pass copies every input in, runs the batch and copies
+    every output back, in order on one stream).  GSamples/s."""
+    if (precision, host) in _BATCHED_CAPACITY:
+        return _BATCHED_CAPACITY[(precision, host)]
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Batch, Plan, State
     streams = workloads.serving_streams(seed)
@@ -362,12 +391,26 @@ def serving_mix_batched_capacity(torch, precision, seed=1005, reps=5):
         states.append(st)
         out = torch.empty((int(n) // s.P + 1, s.P), dtype=torch.complex64, device="cuda")
         items.append((p, src[: int(n)], out, st))
+    if host:   # each item its own device input, filled from pinned host memory
+        xh = [src[: int(n)].cpu().pin_memory() for n in lens]
+        oh = [torch.empty(o.shape, dtype=o.dtype).pin_memory() for _, _, o, _ in items]
+        items = [(p, torch.empty_like(x, device="cuda"), o, st) for (p, _, o, st), x in zip(items, xh)]
+
+    def one_pass():
+        if host:
+            for (_, xd, _, _), x in zip(items, xh):
+                xd.copy_(x, non_blocking=True)
+        b.execute(items)
+        if host:
+            for (_, _, o, _), x in zip(items, oh):
+                x.copy_(o, non_blocking=True)
+
     b = Batch(precision, max_items=len(items), workspace_bytes=2 << 30)
-    b.execute(items)
+    one_pass()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
-        b.execute(items)
+        one_pass()
     torch.cuda.synchronize()
     cap = float(lens.sum()) * reps / (time.perf_counter() - t)
     b.close()
@@ -375,18 +418,57 @@ def serving_mix_batched_capacity(torch, precision, seed=1005, reps=5):
         st.close()
     for p in plans.values():
         p.close()
-    _BATCHED_CAPACITY[precision] = cap
-    log(f"[bench] serving mix, batched path capacity {precision}: {cap / 1e9:.2f} GS/s")
+    _BATCHED_CAPACITY[(precision, host)] = cap
+    log(f"[bench] serving mix, batched path capacity {precision}{' from host buffers' if host else ''}: "
+        f"{cap / 1e9:.2f} GS/s")
     return cap
 
 
+def serving_check(torch, sv, pool, device, oracle_obj, seed, n_req=16):
+    """Correctness of served output: on 4 fresh logical streams (512, 1024,
+    4096 channels and one more 4096; 8-16 taps), 16 requests each of
+    log-uniform length 2^12-2^18 taken from the request pool; the
+    concatenated outputs of each stream against the FP64 oracle on the
+    concatenated input, at sampled frames."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    cfg = [(512, 12), (1024, 16), (4096, 8), (4096, 16)]
+    size = pool.numel() if device else pool.size
+    reqs = []
+    for P, M in cfg:
+        sid = sv.stream(P, M, "c64")
+        res, xs, pend = 0, [], []
+        for n in np.floor(2.0 ** g.uniform(12.0, 18.0, size=n_req)).astype(np.int64):
+            off = int(g.integers(0, size - n + 1))
+            x = pool[off: off + int(n)]
+            frames = (res + int(n)) // P
+            res = (res + int(n)) % P
+            if device:
+                out = torch.empty((frames, P), dtype=torch.complex64, device="cuda")
+            else:
+                out = np.empty((frames, P), dtype=np.complex64)
+            pend.append((sv.submit(sid, x, out), out))
+            xs.append(x.cpu().numpy() if device else np.array(x))
+        reqs.append((P, M, xs, pend))
+    cases = []
+    for P, M, xs, pend in reqs:
+        outs = []
+        for rid, out in pend:
+            r = sv.wait(rid, timeout_s=120)
+            if r["status"] != 0:
+                raise RuntimeError(f"serving check: request failed with status {r['status']}")
+            outs.append(out.cpu().numpy() if device else out)
+        cases.append((np.concatenate(xs), P, M, np.concatenate(outs)))
+    return sampled_check(oracle_obj, cases, seed + 1)
+
+
 def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005, device=False,
-                  frames_per_step=1024):
+                  frames_per_step=1024, oracle_obj=None):
     """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
     1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
     random stream, length log-uniform 2^16-2^22.  The rate is rho times the
-    batched path's capacity C on the same mix (serving_mix_batched_capacity);
-    the server's own closed-burst capacity is reported beside it.  Latency =
+    batched path's capacity C on the same mix with the same buffer placement
+    (serving_mix_batched_capacity: end to end from pinned host memory, or in
+    HBM); the server's own closed-burst capacity is reported beside it.  Latency =
     done - scheduled arrival, including the host-to-device and device-to-host
     copies (device=True: requests already in HBM, used in place, no copies).
     Device-busy is the summed step time over the open-loop window."""
@@ -394,7 +476,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Server
     streams = workloads.serving_streams(seed)
-    sv = Server(precision, max_streams=len(streams), max_active=32, hbm_budget_bytes=budget_bytes,
+    sv = Server(precision, max_streams=len(streams) + 4, max_active=32, hbm_budget_bytes=budget_bytes,
                 frames_per_step=frames_per_step, use_graph=True, max_channels=4096)
     sids = [sv.stream(s.P, s.M, "c64") for s in streams]
     g = np.random.Generator(np.random.PCG64(seed + 7))
@@ -441,7 +523,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
         sv.wait(rid)
         free_out.append(oi)
     cap_server = float(L.sum()) / (time.perf_counter() - t0)
-    cap = serving_mix_batched_capacity(torch, precision)
+    cap = serving_mix_batched_capacity(torch, precision, host=not device)
     mean_len = float(np.mean(lens(100000)))
     lam = rho * cap / mean_len
     # open loop
@@ -495,6 +577,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     gc.enable()
     t_total = time.perf_counter() - t_start - arrivals[n_warm - 1] if n_warm else time.perf_counter() - t_start
     st = sv.stats()
+    check = serving_check(torch, sv, pool, device, oracle_obj, seed + 3) if oracle_obj is not None else None
     sv.close()
     m = np.array(lat[n_warm:], dtype=np.float64)
     pa = np.array(parts[n_warm:], dtype=np.float64)
@@ -503,7 +586,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     return {"precision": precision, "hbm_budget_bytes": budget_bytes, "rho": rho,
             "buffers": "device (in place)" if device else "host (pinned; copied in and out)",
             "frames_per_step": frames_per_step,
-            "capacity_gsps_batched_path": round(cap / 1e9, 3),
+            "capacity_gsps_batched_path": round(cap / 1e9, 3), "capacity_includes_copies": not device,
             "capacity_gsps_server_closed_burst": round(cap_server / 1e9, 3), "rate_req_per_s": round(lam, 1),
             "mean_request_samples": round(mean_len), "requests_measured": n_meas, "warmup_requests": n_warm,
             "p50_ms": round(float(np.percentile(m, 50)), 3), "p99_ms": round(float(np.percentile(m, 99)), 3),
@@ -514,7 +597,15 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
             "admission_waits": st["admission_waits"], "steps": st["steps"],
             "device_busy_frac_open_loop": round((st["device_busy_ms"] - st0["device_busy_ms"]) /
                                                 ((st["now_us"] - st0["now_us"]) / 1e3), 3),
-            "submitter_blocked_on_output_buffers": blocked[0], "latency_parts": breakdown}
+            "submitter_blocked_on_output_buffers": blocked[0], "latency_parts": breakdown, "check": check}
+
+
+def check_oracle():
+    """The FP64 oracle, for the sampled output checks of the batched and
+    serving legs (test infrastructure: it checks the GPU output, computes none
+    of it)."""
+    from oracle import Oracle
+    return Oracle()
 
 
 def main():
@@ -526,7 +617,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
-    ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored",
+    ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored,fp32/compensated",
                     help="comma-separated precision forms of the form tables (form or form/factored)")
     ap.add_argument("--form-workloads", default="real,wide",
                     help="comma-separated workloads of the form tables: real (1024-channel real stream), "
@@ -629,13 +720,14 @@ def main():
         result["ops"] = ops_bench(torch)
     if not args.no_batched:
         log("[bench] batched ragged workload")
-        result["batched"] = batched_bench(torch)
+        result["batched"] = batched_bench(torch, oracle_obj=check_oracle())
     if not args.no_serving:
         log("[bench] serving workload")
-        result["serving"] = [serving_bench(torch, prec, bud) for prec in ("fp8", "bf16x3")
+        o = check_oracle()
+        result["serving"] = [serving_bench(torch, prec, bud, oracle_obj=o) for prec in ("fp8", "bf16x3")
                              for bud in (8 << 30, 256 << 20)]
-        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho) for rho in (0.5, 0.8)
-                              for prec in ("fp8", "bf16x3")]
+        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho, oracle_obj=o)
+                              for rho in (0.5, 0.8) for prec in ("fp8", "bf16x3")]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")

@@ -151,8 +151,22 @@ typedef struct tina_pfb_desc {
  *                      TINA_DFT_DENSE.  FP32, taps <= 16, single-stream
  *                      execute; a call whose input is not 16-byte aligned (or
  *                      whose residue leaves the history a partial float4) runs
- *                      the two-kernel path instead. */
-typedef enum tina_dft_algorithm { TINA_DFT_DENSE = 0, TINA_DFT_FACTORED = 1, TINA_DFT_FUSED = 2 } tina_dft_algorithm;
+ *                      the two-kernel path instead.
+ *   TINA_DFT_COMPENSATED the dense FP32 product with compensated accumulation
+ *                      over K: each K tile of 32 products is summed on its
+ *                      own, and the tile sums are added to the running sum
+ *                      with an error-free two-sum whose rounding error is
+ *                      carried into the next tile.  The error of a channel
+ *                      then scales with the partial sums of one tile instead
+ *                      of the whole row, which keeps channels far below the
+ *                      frame's strongest one accurate (Eq. (12) at a wide
+ *                      dynamic range).  FP32 only; single-stream execute. */
+typedef enum tina_dft_algorithm {
+    TINA_DFT_DENSE = 0,
+    TINA_DFT_FACTORED = 1,
+    TINA_DFT_FUSED = 2,
+    TINA_DFT_COMPENSATED = 3
+} tina_dft_algorithm;
 
 typedef struct tina_pfb_plan_s* tina_pfb_plan_t;
 typedef struct tina_pfb_state_s* tina_pfb_state_t;

@@ -215,11 +215,21 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int
 // inverse DFT takes its FP32 channel frames this way).  The analysis bank's
 // reduced forms take A in operand form from the FIR (gemm_tile_raw).  Called
 // by every thread of the block.
-template <int FORM, int WN>
+//
+// COMP (FP32): compensated K accumulation.  Each K tile's products go to
+// block accumulators blk; at the tile's end the block sum is added to the
+// running sum acc by an error-free transformation (Knuth's TwoSum), and the
+// rounding error of that addition is where the next tile's block accumulation
+// starts.  The error of the result is then that of summing one K tile (32
+// products) plus one rounding per tile, instead of a rounding at the size of
+// the whole running sum for each of the K products: channels far below the
+// frame's strongest one keep their accuracy.
+template <int FORM, int WN, bool COMP = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM, WN>& sm) {
     constexpr int BN = 64 * WN, WC = 32 * WN;  // block tile columns, columns per wave
     using ft = FT<FORM>;
     static_assert(FORM == FORM_FP32 || FORM == FORM_BF16 || FORM == FORM_BF16X3, "FP32 A, converted to bf16 at most");
+    static_assert(!COMP || FORM == FORM_FP32, "compensated accumulation: FP32 products");
     constexpr int NP = ft::NP, EB = ft::EB, SLAB = ft::SLAB;
     constexpr int CPR = ROWB / 16;                // 16-byte chunks per row
     constexpr int BK = ROWB / EB;                 // K elements per tile
@@ -290,7 +300,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
             }
     };
 
-    f32x16 acc[2][WN], acc2[2][WN];
+    f32x16 acc[2][WN], acc2[2][WN];  // COMP: acc2 = the block accumulators
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -327,13 +337,35 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                         bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + off(q));
                     }
             const int sa[2] = {0, 0}, sb[WN] = {};
-            mfma_slab<FORM, NP, RD, WN>(af, bf, acc, acc2, sa, sb);
+            if constexpr (COMP) mfma_slab<FORM, NP, RD, WN>(af, bf, acc2, acc, sa, sb);
+            else mfma_slab<FORM, NP, RD, WN>(af, bf, acc, acc2, sa, sb);
+        }
+        if constexpr (COMP) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const float a = acc[i][j][v], b = acc2[i][j][v];
+                        const float sum = a + b, bv = sum - a;
+                        acc2[i][j][v] = (a - (sum - bv)) + (b - bv);
+                        acc[i][j][v] = sum;
+                    }
         }
         __syncthreads();
         if (t + 1 < nk) {
             store_tile();
             __syncthreads();
         }
+    }
+    if constexpr (COMP) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[i][j][v] += acc2[i][j][v];
     }
 
     gemm_epilogue<FORM, WN>(g, m0, n0, acc, acc2, nullptr);
@@ -1064,6 +1096,19 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     gemm_tile<FORM, WN>(g, m0, n0, sm);
 }
 
+// FP32 with compensated K accumulation: 128 x 128 tiles (the running sums
+// and the block accumulators of 2 x 2 MFMA blocks per wave fit 2 waves per
+// SIMD, so one wave's additions overlap the other's products).
+template <int WN>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void dft_gemm_comp_kernel(GemmArgs g) {
+    constexpr int BN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) GemmSmem<FORM_FP32, WN> sm;
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, BN, m0, n0);
+    gemm_tile<FORM_FP32, WN, true>(g, m0, n0, sm);
+}
+
 // Held to 2 waves per SIMD: the fp16 hi + lo form with its second accumulator
 // otherwise took 331 registers and one wave (2 waves with 4 spilled registers
 // measured 10-20% faster); the other forms fit 2 waves anyway.
@@ -1265,6 +1310,13 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
             case FORM_FP16X3: return (g.fexp && g.Aq1) ? launch_raw<FORM_FP16X3>(g, s) : hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
+    }
+    if (g.compensated) {
+        if (g.form != FORM_FP32) return hipErrorInvalidValue;
+        constexpr int WN = 2, BN = 64 * WN;
+        const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+        hipLaunchKernelGGL((dft_gemm_comp_kernel<WN>), dim3((unsigned)(nm * nn)), dim3(NT), 0, s, g);
+        return hipGetLastError();
     }
     switch (g.form) {
         case FORM_FP32: return launch_form<FORM_FP32>(g, s);

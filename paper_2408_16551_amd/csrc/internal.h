@@ -103,6 +103,7 @@ struct GemmArgs {
     const uint8_t* Aq1;
     const uint8_t* Aqs;
     const int32_t* fexp;   // per-frame scaled forms with A in operand form: A row f carries 2^-fexp[f]
+    int32_t compensated;   // FP32 only: compensated K accumulation (TwoSum per K tile)
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
 // The FIR fused into the FP32 GEMM (g.A unused; x describes the input stream

@@ -44,7 +44,8 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: struct_size too small");
     const int64_t ws_req = d->struct_size >= offsetof(tina_pfb_desc, dft_algorithm) ? d->workspace_bytes : 0;
     const int dft_alg = d->struct_size >= offsetof(tina_pfb_desc, reserved_) ? d->dft_algorithm : TINA_DFT_DENSE;
-    if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED && dft_alg != TINA_DFT_FUSED)
+    if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED && dft_alg != TINA_DFT_FUSED &&
+        dft_alg != TINA_DFT_COMPENSATED)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown dft_algorithm");
     if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
@@ -73,6 +74,8 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     if (dft_alg == TINA_DFT_FACTORED && d->output == TINA_OUT_PFB &&
         (d->precision != TINA_PREC_FP32 || !fft_supported(d->channels)))
         return fail(TINA_ERR_UNSUPPORTED, "plan: the factored DFT needs FP32 and 256 <= channels <= 4096");
+    if (dft_alg == TINA_DFT_COMPENSATED && d->output == TINA_OUT_PFB && d->precision != TINA_PREC_FP32)
+        return fail(TINA_ERR_UNSUPPORTED, "plan: compensated accumulation needs FP32");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TINA_ERR_DEVICE, "plan: no HIP device");
     if (d->device < 0 || d->device >= ndev) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: bad device ordinal");
@@ -350,6 +353,7 @@ tina_status execute_with(tina_pfb_plan_s* p, const void* d_in, int64_t n, void* 
             ga.Aq1 = fa.q1;
             ga.Aqs = fa.qs;
             ga.fexp = fa.fexp;
+            ga.compensated = p->dft_algorithm == TINA_DFT_COMPENSATED;
             HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
     }

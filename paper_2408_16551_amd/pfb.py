@@ -224,7 +224,7 @@ class Plan:
         d.sample_type, d.window = SAMPLE[sample_type], WINDOW[window]
         d.precision, d.output, d.device = PRECISION[precision], OUTPUT[output], int(device)
         d.workspace_bytes = int(workspace_bytes)
-        d.dft_algorithm = {"dense": 0, "factored": 1, "fused": 2}[dft]
+        d.dft_algorithm = {"dense": 0, "factored": 1, "fused": 2, "compensated": 3}[dft]
         self._custom = None
         if custom_taps is not None:
             self._custom = np.ascontiguousarray(custom_taps, dtype=np.float64)

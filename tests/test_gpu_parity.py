@@ -17,7 +17,9 @@ torch = pytest.importorskip("torch")
 FP32_BOUND = 1e-5
 # Relative-L2 bounds of the reduced forms vs the FP64 oracle: the measured error
 # rounded up (the error model: unit roundoff of the operand format per operand).
-REDUCED_BOUNDS = {"bf16": 8e-3, "bf16x3": 2e-5, "fp16": 1e-3, "fp16x3": 1e-6, "fp8": 0.1, "mxfp8": 0.05}
+# Split bf16 (hi*hi + hi*lo + lo*hi) is held to 1e-5, the bar at which it must
+# beat plain FP32 on speed (measured 3.9e-6 on both workload shapes).
+REDUCED_BOUNDS = {"bf16": 8e-3, "bf16x3": 1e-5, "fp16": 1e-3, "fp16x3": 1e-6, "fp8": 0.1, "mxfp8": 0.05}
 
 
 def rel_l2(got, ref):
@@ -276,9 +278,10 @@ def _sample_frames(F, M, n_extra, seed):
     return np.array(sorted(fr), dtype=np.int64)
 
 
-def test_full_size_real_stream_fp32_sampled(oracle, real_stream_wl):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_size_real_stream_sampled(oracle, real_stream_wl, precision):
     w = real_stream_wl
-    plan = _plan(w.P, w.M, False)
+    plan = _plan(w.P, w.M, False, precision=precision)
     xd = _dev(w.x)
     X = plan(xd)
     torch.cuda.synchronize()
@@ -286,26 +289,58 @@ def test_full_size_real_stream_fp32_sampled(oracle, real_stream_wl):
     assert X.shape == (F, w.P // 2 + 1)
     fr = _sample_frames(F, w.M, 48, seed=1)
     got = X[torch.from_numpy(fr).cuda()].cpu().numpy()
-    ref = oracle.pfb(w.x, w.P, w.M, oracle.window(w.P, w.M, w.window), frames=fr)
-    assert rel_l2(got, ref) < FP32_BOUND
+    key = ("real", fr.tobytes())
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.pfb(w.x, w.P, w.M, oracle.window(w.P, w.M, w.window), frames=fr)
+    err = rel_l2(got, _ORACLE_CACHE[key])
+    print(f"real stream {precision}: rel_l2={err:.3e}")
+    assert err < (FP32_BOUND if precision == "fp32" else REDUCED_BOUNDS[precision])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "fp8", "mxfp8"])
-def test_full_size_wide_dynamic_range_sampled(oracle, precision, wide_wl):
+# Worst channel's relative L2 error on the 60 dB workload (4096 complex
+# channels, sampled frames past the warm-up).  Its noise-only channels lie
+# about 120 dB (a power ratio near 1e12) below the strongest tone's channel, so
+# an error floor relative to the strongest channel shows there magnified about
+# 1e6: the reduced operand forms' rounding of the FIR output, and in FP32 the
+# accumulation over K of a row whose partial sums carry the strong tone.
+# Bounds: the measured worst channel rounded up by half.  Compensated
+# accumulation (error-free two-sum per K tile) brings FP32 under 1e-2.
+WORST_CHANNEL_BOUNDS = {"fp32": 0.16, "fp32/factored": 0.11, "fp32/compensated": 1e-2, "bf16": 180.0,
+                        "bf16x3": 0.37, "fp16": 28.0, "fp16x3": 0.06, "fp8": 5800.0, "mxfp8": 5800.0}
+
+
+def worst_channel(got, ref, fr, M):
+    keep = fr >= M - 1
+    g = np.asarray(got, dtype=np.complex128)[keep]
+    r = np.asarray(ref, dtype=np.complex128)[keep]
+    num = np.sqrt((np.abs(g - r) ** 2).sum(axis=0))
+    den = np.sqrt((np.abs(r) ** 2).sum(axis=0))
+    ratio = num / den
+    return float(ratio.max()), int(ratio.argmax())
+
+
+@pytest.mark.parametrize("entry", list(WORST_CHANNEL_BOUNDS))
+def test_full_size_wide_dynamic_range_sampled(oracle, entry, wide_wl):
+    from paper_2408_16551_amd.pfb import Plan
     w = wide_wl
-    plan = _plan(w.P, w.M, True, window=w.window, precision=precision)
+    precision, dft = (entry.split("/") + ["dense"])[:2]
+    print(f"wide dynamic range: {entry} P={w.P} M={w.M} N={w.x.size}", flush=True)
+    plan = Plan(w.P, w.M, "c64", w.window, precision, dft=dft)
     X = plan(_dev(w.x))
     torch.cuda.synchronize()
     F = w.x.size // w.P
     fr = _sample_frames(F, w.M, 24, seed=2)
     got = X[torch.from_numpy(fr).cuda()].cpu().numpy()
+    plan.close()
     key = ("wide", fr.tobytes())
     if key not in _ORACLE_CACHE:
         _ORACLE_CACHE[key] = oracle.pfb(w.x, w.P, w.M, oracle.window(w.P, w.M, w.window), frames=fr)
     ref = _ORACLE_CACHE[key]
     err = rel_l2(got, ref)
-    print(f"wide dynamic range {precision}: rel_l2={err:.3e}")
+    wc, k = worst_channel(got, ref, fr, w.M)
+    print(f"wide dynamic range {entry}: rel_l2={err:.3e} worst channel {k}: {wc:.3e}")
     assert err < (FP32_BOUND if precision == "fp32" else REDUCED_BOUNDS[precision])
+    assert wc < WORST_CHANNEL_BOUNDS[entry]
 
 
 # ---------------------------------------------------------------- factored DFT
@@ -348,19 +383,38 @@ def test_factored_rejects_unsupported():
         assert e.value.status == 2
 
 
-def test_full_size_wide_dynamic_range_factored_sampled(oracle, wide_wl):
+# ------------------------------------------------- compensated accumulation
+@pytest.mark.parametrize("P,M,cplx,frames", [(64, 4, True, 300), (256, 8, True, 130), (1024, 16, False, 200),
+                                              (1024, 16, True, 61), (4096, 8, True, 40), (8192, 2, False, 9)])
+def test_compensated_dft_matches_oracle(oracle, P, M, cplx, frames):
     from paper_2408_16551_amd.pfb import Plan
-    w = wide_wl
-    plan = Plan(w.P, w.M, "c64", w.window, "fp32", dft="factored")
-    X = plan(_dev(w.x))
-    torch.cuda.synchronize()
-    F = w.x.size // w.P
-    fr = _sample_frames(F, w.M, 24, seed=2)
-    got = X[torch.from_numpy(fr).cuda()].cpu().numpy()
-    key = ("wide", fr.tobytes())
-    if key not in _ORACLE_CACHE:
-        _ORACLE_CACHE[key] = oracle.pfb(w.x, w.P, w.M, oracle.window(w.P, w.M, w.window), frames=fr)
-    assert rel_l2(got, _ORACLE_CACHE[key]) < FP32_BOUND
+    N = P * frames + P // 3
+    x = _rand(N, cplx, seed=23 * P + M)
+    print(f"compensated P={P} M={M} cplx={cplx} frames={frames}", flush=True)
+    plan = Plan(P, M, "c64" if cplx else "r32", "hann", "fp32", dft="compensated")
+    X = _run(plan, x)
+    ref = oracle.pfb(x[: (N // P) * P], P, M, oracle.window(P, M, "hann"))
+    err = rel_l2(X, ref)
+    print(f"compensated P={P} M={M} cplx={cplx}: rel_l2={err:.3e}")
+    assert err < FP32_BOUND / 4   # below the dense FP32 product's error
+    if not cplx:
+        assert np.all(X[:, 0].imag == 0) and np.all(X[:, -1].imag == 0)
+
+
+def test_compensated_streaming_bitwise_and_rejects_reduced_forms():
+    from paper_2408_16551_amd.pfb import Plan, State, TinaError
+    P, M = 512, 12
+    N = P * 300 + 77
+    x = _rand(N, True, seed=9)
+    plan = Plan(P, M, "c64", "hann", "fp32", dft="compensated")
+    one = _run(plan, x)
+    st = State(plan)
+    cuts = [0, 500, P * 7, P * 150 + 3, N]
+    got = np.concatenate([_run(plan, np.ascontiguousarray(x[a:b]), state=st) for a, b in zip(cuts[:-1], cuts[1:])])
+    assert np.array_equal(got, one)
+    with pytest.raises(TinaError) as e:
+        Plan(P, M, "c64", "hann", "bf16x3", dft="compensated")
+    assert e.value.status == 2
 
 
 # ------------------------------------------------------- synthesis (inverse) bank
