@@ -131,6 +131,23 @@ __device__ __forceinline__ void mfma_block(const uint4 (&af)[TM][NP][RD], const 
     }
 }
 
+// FP8 E4M3 product with E8M0 scales taken from byte oa of sa and byte ob of
+// sb (the instruction's scale operand selectors are immediates: after
+// unrolling oa and ob are constants and the switch folds away).
+__device__ __forceinline__ f32x16 mfma_f8_scaled_sel(const i32x8& a, const i32x8& b, const f32x16& c, int sa, int sb,
+                                                     int oa, int ob) {
+#define TINA_MX_CASE(A, B) \
+    case A * 4 + B: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, A, sa, B, sb);
+    switch (oa * 4 + ob) {
+        TINA_MX_CASE(0, 0) TINA_MX_CASE(0, 1) TINA_MX_CASE(0, 2) TINA_MX_CASE(0, 3)
+        TINA_MX_CASE(1, 0) TINA_MX_CASE(1, 1) TINA_MX_CASE(1, 2) TINA_MX_CASE(1, 3)
+        TINA_MX_CASE(2, 0) TINA_MX_CASE(2, 1) TINA_MX_CASE(2, 2) TINA_MX_CASE(2, 3)
+        TINA_MX_CASE(3, 0) TINA_MX_CASE(3, 1) TINA_MX_CASE(3, 2) default: break;
+    }
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 3, sa, 3, sb);
+#undef TINA_MX_CASE
+}
+
 template <int FORM, int NP, int RD, int WN>
 __device__ __forceinline__ void mfma_slab(const uint4 (&af)[2][NP][RD], const uint4 (&bf)[WN][NP][RD],
                                           f32x16 (&acc)[2][WN], f32x16 (&acc2)[2][WN], const int (&sa)[2],
@@ -728,20 +745,25 @@ struct WideGeom {
     static constexpr int BK = ROWB / EB;    // K elements per tile
     static constexpr int NSLAB = ROWB / SLAB;
     static_assert(BM * CPR % NTH == 0 && BN * CPR % NTH == 0, "whole chunks per thread");
-    static constexpr int SCW = (BM + BN + NTH - 1) / NTH;  // scale words per thread (block-scaled form)
     static_assert(NSLAB >= 1, "a K tile holds whole MFMA slabs");
 };
 
-// Scale words (block-scaled form) and frame scales (per-frame scaled forms)
+// Scale groups (block-scaled form) and frame scales (per-frame scaled forms)
 // as empty bases when unused, so the bf16 hi + lo form's two stages fill the
-// 160 KiB of LDS exactly.
-template <int N, bool ON> struct WideMx { uint32_t mxs[2][N]; };
-template <int N> struct WideMx<N, false> {};
+// 160 KiB of LDS exactly.  A scale group holds the E8M0 scales of 8 K tiles
+// arranged for the MFMA's scale operand: for K tile k, wave row (column)
+// block w, lane row r and lane half h, one word whose byte x is the scale of
+// MFMA block row (column) x -- the block's operand selector picks it.
+template <int WGM, int WGN, bool ON> struct WideMx {
+    uint32_t mxa[2][8][WGM][64];
+    uint32_t mxb[2][8][WGN][64];
+};
+template <int WGM, int WGN> struct WideMx<WGM, WGN, false> {};
 template <int N, bool ON> struct WideFsc { float fsc[N]; };
 template <int N> struct WideFsc<N, false> {};
 
 template <int FORM>
-struct WideSmem : WideMx<WideGeom<FORM>::BM + WideGeom<FORM>::BN, FT<FORM>::MX>,
+struct WideSmem : WideMx<WideGeom<FORM>::WGM, WideGeom<FORM>::WGN, FT<FORM>::MX>,
                   WideFsc<WideGeom<FORM>::BM, FT<FORM>::SCALED> {
     uint8_t tiles[2][WideGeom<FORM>::STAGE];
 };
@@ -793,46 +815,49 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
     struct Stage {
         uint4 a[NP][QCH];
         uint4 b[NP][BCH];
-        uint32_t sc[G::SCW];
     };
-    // Block-scaled form: the 2 scale bytes of each row's 64-K tile (K % 128
-    // == 0), A rows then B rows, staged like the codes.  When a row's scales
-    // are a whole number of 16-byte groups (K % 512 == 0), a group -- the
-    // scales of 8 K tiles -- is loaded once into registers and each tile takes
-    // its 2 bytes from there: row-strided 2-byte loads per tile cost as much
-    // L2 traffic (a cache line per row) as half the codes.
-    uint4 scg[G::SCW];
-    const bool sc_grouped = nb % 16 == 0;
-    auto load_scales = [&](Stage& r, int k0) {
-        if constexpr (ft::MX) {
-            static_assert(G::ROWB == 64, "two scale bytes per row and K tile");
-            const int kt = k0 / 64;  // K tile index
-#pragma unroll
-            for (int w = 0; w < G::SCW; ++w) {
-                const int row = tid + w * NTH;
-                const uint8_t* src = nullptr;
-                if (row < BM) {
-                    if (m0 + row < g.F) src = g.Aqs + (m0 + row) * nb;
-                } else if (row < BM + BN) {
-                    if (n0 + row - BM < g.N) src = (const uint8_t*)g.B1 + (n0 + row - BM) * nb;
-                }
-                if (sc_grouped) {
-                    if ((kt & 7) == 0)
-                        scg[w] = src ? *reinterpret_cast<const uint4*>(src + kt * 2) : make_uint4(~0u, ~0u, ~0u, ~0u);
-                    const int q = (kt & 7) >> 1;
-                    const uint32_t word = q == 0 ? scg[w].x : q == 1 ? scg[w].y : q == 2 ? scg[w].z : scg[w].w;
-                    r.sc[w] = src ? (word >> (16 * (kt & 1))) & 0xffffu : 0x7f7fu;
-                } else {
-                    r.sc[w] = src ? *reinterpret_cast<const uint16_t*>(src + kt * 2) : 0x7f7fu;
-                }
-            }
+    // Block-scaled form: the scale bytes of a row (2 per 64-K tile, K % 128
+    // == 0) move in groups of 16 bytes -- 8 K tiles -- one row per thread (A
+    // rows, then B rows), through two LDS group buffers chosen by group
+    // parity.  Group g + 1 is loaded when group g's first tile starts and
+    // stored 4 tiles later, long after the last reads of group g - 1 from the
+    // same buffer and long before group g + 1's first reads; the lane then
+    // reads its byte for the K tile and lane half straight into the scale
+    // operand.  Buffer loads: bytes past a row's end are the next row's (for K
+    // tiles that do not exist), past the last row zero.
+    const int ng = ((g.K + BK - 1) / BK + 7) / 8;  // scale groups (block-scaled form)
+    __amdgpu_buffer_rsrc_t rsc = ra[0];
+    uint32_t vsc = 0;
+    uint4 scn = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (ft::MX) {
+        static_assert(BM + BN == NTH && BM % 64 == 0 && G::ROWB == 64 && TM <= 4 && TN <= 4,
+                      "one scale row per thread, whole waves per operand, a scale byte per MFMA block");
+        const int64_t ar = g.F - m0 < BM ? g.F - m0 : BM, br = g.N - n0 < BN ? g.N - n0 : BN;
+        if (__builtin_amdgcn_readfirstlane(wave) < BM / 64) {
+            rsc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.Aqs + m0 * nb), (short)0, (int)(ar * nb), 0x00020000);
+            vsc = (uint32_t)(tid * nb);
+        } else {
+            rsc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>((const uint8_t*)g.B1 + n0 * nb), (short)0,
+                                                    (int)(br * nb), 0x00020000);
+            vsc = (uint32_t)((tid - BM) * nb);
         }
+    }
+    auto load_group = [&](int gi) {
+        return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rsc, vsc, gi * 16, 0));
     };
-    auto store_scales = [&](const Stage& r, int buf) {
+    auto store_group = [&](int slot, uint4 v) {
         if constexpr (ft::MX) {
+            // This thread's row: block x of wave row (column) block w, lane row r.
+            const bool isa = __builtin_amdgcn_readfirstlane(wave) < BM / 64;
+            const int rr = isa ? tid : tid - BM, r = rr & 31, x = (rr >> 5) % (isa ? TM : TN), w = (rr >> 5) / (isa ? TM : TN);
+            uint8_t* base = reinterpret_cast<uint8_t*>(isa ? &sm.mxa[slot][0][w][0] : &sm.mxb[slot][0][w][0]);
+            const int kstride = 4 * 64 * (isa ? G::WGM : G::WGN);   // bytes from one K tile to the next
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int w = 0; w < G::SCW; ++w)
-                if (tid + w * NTH < BM + BN) sm.mxs[buf][tid + w * NTH] = r.sc[w];
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    base[k * kstride + (2 * r + h) * 4 + x] = (uint8_t)(wv[k >> 1] >> (8 * (2 * (k & 1) + h)));
         }
     };
     auto load = [&](Stage& r, int k0) {
@@ -846,7 +871,6 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
             for (int i = 0; i < BCH; ++i)
                 r.b[p][i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rbs[p], vb[i], kb0, 0));
         }
-        load_scales(r, k0);
     };
     auto store = [&](const Stage& r, int buf) {
         uint8_t* As = sm.tiles[buf];
@@ -864,7 +888,6 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
                 *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = r.b[p][i];
             }
         }
-        store_scales(r, buf);
     };
 
     f32x16 acc[TM][TN], acc2[TM][TN];
@@ -910,29 +933,25 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
             }
         };
         FragT a[4][NP], b[2][TN][NP];
-        int sa[2][TM], sb[2][TN];
+        int sa[2], sb[2];  // block-scaled form: scale words, byte x for MFMA block row / column x
         auto rdA = [&](int buf, int u, FragT (&d)[NP]) {
 #pragma unroll
             for (int p = 0; p < NP; ++p)
                 d[p] = rd(sm.tiles[buf] + p * BM * RS + ((wm * TM + u % TM) * 32 + lr) * RS + (u / TM) * SLAB + lh * 16);
         };
-        auto rdB = [&](int buf, int sl, int par) {
+        auto rdB = [&](int buf, int sl, int par, int kt) {
             const uint8_t* Bs = sm.tiles[buf] + NP * BM * RS;
 #pragma unroll
             for (int bn = 0; bn < TN; ++bn)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
                     b[par][bn][p] = rd(Bs + p * BN * RS + ((wn * TN + bn) * 32 + lr) * RS + sl * SLAB + lh * 16);
-#pragma unroll
-            for (int x = 0; x < TM; ++x) sa[par][x] = 0x7f7f7f7f;
-#pragma unroll
-            for (int x = 0; x < TN; ++x) sb[par][x] = 0x7f7f7f7f;
-            if constexpr (ft::MX) {  // byte 2 sl + lh of the row's scale bytes: the lane half's 32-K block
-                const int sh = 8 * (2 * sl + lh);
-#pragma unroll
-                for (int x = 0; x < TM; ++x) sa[par][x] = (int)(sm.mxs[buf][(wm * TM + x) * 32 + lr] >> sh);
-#pragma unroll
-                for (int x = 0; x < TN; ++x) sb[par][x] = (int)(sm.mxs[buf][BM + (wn * TN + x) * 32 + lr] >> sh);
+            sa[par] = 0x7f7f7f7f;
+            sb[par] = 0x7f7f7f7f;
+            if constexpr (ft::MX) {  // K tile kt (one slab): the lane's row, the lane half's 32-K block
+                const int slot = (kt >> 3) & 1;
+                sa[par] = (int)sm.mxa[slot][kt & 7][wm][2 * lr + lh];
+                sb[par] = (int)sm.mxb[slot][kt & 7][wn][2 * lr + lh];
             }
         };
         auto mf = [&](int u, int par) {
@@ -955,9 +974,8 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
                         else
                             acc2[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x),
                                                                                   __builtin_bit_cast(f16x8, y), acc2[bm][bn], 0, 0, 0);
-                    } else {  // FP8 E4M3 operands (formats 0/0) with unit or block scales
-                        acc[bm][bn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[bm][bn], 0, 0, 0,
-                                                                                      sa[par][bm], 0, sb[par][bn]);
+                    } else {  // FP8 E4M3 operands (formats 0/0) with unit or block scales, byte bm / bn of the scale words
+                        acc[bm][bn] = mfma_f8_scaled_sel(x, y, acc[bm][bn], sa[par], sb[par], bm, bn);
                     }
                 }
         };
@@ -975,7 +993,7 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
 #pragma unroll
             for (int u = 0; u < U - 2; ++u) {
                 const int u2 = u + 2, s2 = u2 / TM;
-                if (u2 % TM == 0) rdB(tt, s2, (par0 + s2) & 1);
+                if (u2 % TM == 0) rdB(tt, s2, (par0 + s2) & 1, t);
                 rdA(tt, u2, a[u2 % 4]);
                 // The next tile's LDS stores and the loads of the tile after
                 // it, CPU chunks per unit, each chunk's load reissued right
@@ -998,16 +1016,17 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
                     }
                 }
                 if constexpr (ft::MX) {
-                    if (u == 0) {
-                        store_scales(r, nbuf);
-                        load_scales(r, t2 * BK);
+                    const int gi = t >> 3;
+                    if (u == 0 && gi >= 1 && gi + 1 < ng) {
+                        if ((t & 7) == 0) scn = load_group(gi + 1);
+                        if ((t & 7) == 4) store_group((gi + 1) & 1, scn);
                     }
                 }
                 mf(u, (par0 + u / TM) & 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
-            rdB(nbuf, 0, (par0 + NSLAB) & 1);
+            rdB(nbuf, 0, (par0 + NSLAB) & 1, t + 1);
             rdA(nbuf, 0, a[0]);
             rdA(nbuf, 1, a[1]);
             mf(U - 2, (par0 + NSLAB - 1) & 1);
@@ -1018,12 +1037,21 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
             // Both first tiles' loads in flight together: one memory latency
             // before the first products, not two.
             Stage r0;
+            uint4 g0, g1;
+            if constexpr (ft::MX) {
+                g0 = load_group(0);
+                g1 = ng > 1 ? load_group(1) : g0;
+            }
             load(r0, 0);
             load(r, (nk > 1 ? 1 : 0) * BK);
             store(r0, 0);
+            if constexpr (ft::MX) {
+                store_group(0, g0);
+                store_group(1, g1);
+            }
         }
         __syncthreads();
-        rdB(0, 0, 0);
+        rdB(0, 0, 0, 0);
         rdA(0, 0, a[0]);
         rdA(0, 1, a[1]);
         for (int t = 0; t < nk; t += 2) {
