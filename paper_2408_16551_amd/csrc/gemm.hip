@@ -719,12 +719,12 @@ __device__ __forceinline__ void gemm_tile_raw(const GemmArgs& g, int64_t m0, int
 // need as many LDS bytes per cycle as the LDS delivers).  One block per CU:
 // two LDS stages of K tiles (one barrier per K tile), the next tile's global
 // loads in flight in registers during a whole K tile of products.
-// ROWB: bytes of an operand row per K tile and piece.  The FP8 forms take one
-// 64-K slab per K tile: with two, the compiler keeps both slabs' 32-byte
-// fragments live across the next tile's LDS stores and runs out of registers.
+// ROWB: bytes of an operand row per K tile and piece (two 64-K slabs for
+// per-frame FP8; one for block-scaled FP8, whose scale words with two slabs'
+// fragments would not fit the registers).
 template <int FORM> struct WideCfg {  // 256 x 256 tiles, waves of 128 x 64
     static constexpr int WGM = 2, WGN = 4, TM = 4, TN = 2;
-    static constexpr int ROWB = FT<FORM>::EB == 1 ? 64 : 128 / FT<FORM>::NP;
+    static constexpr int ROWB = FORM == FORM_MXFP8 ? 64 : 128 / FT<FORM>::NP;
 };
 template <> struct WideCfg<FORM_FP16X3> {  // two accumulators: 128 x 256 tiles, waves of 64 x 64
     static constexpr int WGM = 2, WGN = 4, TM = 2, TN = 2, ROWB = 64;
@@ -750,13 +750,14 @@ struct WideGeom {
 
 // Scale groups (block-scaled form) and frame scales (per-frame scaled forms)
 // as empty bases when unused, so the bf16 hi + lo form's two stages fill the
-// 160 KiB of LDS exactly.  A scale group holds the E8M0 scales of 8 K tiles
-// arranged for the MFMA's scale operand: for K tile k, wave row (column)
-// block w, lane row r and lane half h, one word whose byte x is the scale of
-// MFMA block row (column) x -- the block's operand selector picks it.
+// 160 KiB of LDS exactly.  A scale group holds the E8M0 scales of 8 64-K
+// slabs arranged for the MFMA's scale operand: for slab k, wave row (column)
+// block w, lane row r and lane half h, one word (half-word for the two column
+// blocks) whose byte x is the scale of MFMA block row (column) x -- the
+// block's operand selector picks it.
 template <int WGM, int WGN, bool ON> struct WideMx {
     uint32_t mxa[2][8][WGM][64];
-    uint32_t mxb[2][8][WGN][64];
+    uint16_t mxb[2][8][WGN][64];
 };
 template <int WGM, int WGN> struct WideMx<WGM, WGN, false> {};
 template <int N, bool ON> struct WideFsc { float fsc[N]; };
@@ -816,21 +817,22 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
         uint4 a[NP][QCH];
         uint4 b[NP][BCH];
     };
-    // Block-scaled form: the scale bytes of a row (2 per 64-K tile, K % 128
-    // == 0) move in groups of 16 bytes -- 8 K tiles -- one row per thread (A
-    // rows, then B rows), through two LDS group buffers chosen by group
-    // parity.  Group g + 1 is loaded when group g's first tile starts and
-    // stored 4 tiles later, long after the last reads of group g - 1 from the
-    // same buffer and long before group g + 1's first reads; the lane then
-    // reads its byte for the K tile and lane half straight into the scale
+    // Block-scaled form: the scale bytes of a row (2 per 64-K slab, K % 128
+    // == 0) move in groups of 16 bytes -- 8 slabs, SPG K tiles -- one row per
+    // thread (A rows, then B rows), through two LDS group buffers chosen by
+    // group parity.  Group g + 1 is loaded when group g's first tile starts
+    // and stored SPG / 2 tiles later, after the last reads of group g - 1 from
+    // the same buffer and before group g + 1's first reads; the lane then
+    // reads its word for the slab and lane half straight into the scale
     // operand.  Buffer loads: bytes past a row's end are the next row's (for K
     // tiles that do not exist), past the last row zero.
-    const int ng = ((g.K + BK - 1) / BK + 7) / 8;  // scale groups (block-scaled form)
+    constexpr int SPG = 8 / NSLAB;                                        // K tiles per scale group
+    const int ng = ((g.K + BK - 1) / BK + SPG - 1) / SPG;  // scale groups (block-scaled form)
     __amdgpu_buffer_rsrc_t rsc = ra[0];
     uint32_t vsc = 0;
     uint4 scn = make_uint4(0u, 0u, 0u, 0u);
     if constexpr (ft::MX) {
-        static_assert(BM + BN == NTH && BM % 64 == 0 && G::ROWB == 64 && TM <= 4 && TN <= 4,
+        static_assert(BM + BN == NTH && BM % 64 == 0 && 8 % NSLAB == 0 && SPG >= 2 && TM <= 4 && TN <= 2,
                       "one scale row per thread, whole waves per operand, a scale byte per MFMA block");
         const int64_t ar = g.F - m0 < BM ? g.F - m0 : BM, br = g.N - n0 < BN ? g.N - n0 : BN;
         if (__builtin_amdgcn_readfirstlane(wave) < BM / 64) {
@@ -850,14 +852,16 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
             // This thread's row: block x of wave row (column) block w, lane row r.
             const bool isa = __builtin_amdgcn_readfirstlane(wave) < BM / 64;
             const int rr = isa ? tid : tid - BM, r = rr & 31, x = (rr >> 5) % (isa ? TM : TN), w = (rr >> 5) / (isa ? TM : TN);
-            uint8_t* base = reinterpret_cast<uint8_t*>(isa ? &sm.mxa[slot][0][w][0] : &sm.mxb[slot][0][w][0]);
-            const int kstride = 4 * 64 * (isa ? G::WGM : G::WGN);   // bytes from one K tile to the next
+            uint8_t* base = isa ? reinterpret_cast<uint8_t*>(&sm.mxa[slot][0][w][0])
+                                : reinterpret_cast<uint8_t*>(&sm.mxb[slot][0][w][0]);
+            const int wb = isa ? 4 : 2;                           // bytes per entry
+            const int kstride = wb * 64 * (isa ? G::WGM : G::WGN);  // bytes from one 64-K slab to the next
             const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int k = 0; k < 8; ++k)
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
-                    base[k * kstride + (2 * r + h) * 4 + x] = (uint8_t)(wv[k >> 1] >> (8 * (2 * (k & 1) + h)));
+                    base[k * kstride + (2 * r + h) * wb + x] = (uint8_t)(wv[k >> 1] >> (8 * (2 * (k & 1) + h)));
         }
     };
     auto load = [&](Stage& r, int k0) {
@@ -948,10 +952,10 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
                     b[par][bn][p] = rd(Bs + p * BN * RS + ((wn * TN + bn) * 32 + lr) * RS + sl * SLAB + lh * 16);
             sa[par] = 0x7f7f7f7f;
             sb[par] = 0x7f7f7f7f;
-            if constexpr (ft::MX) {  // K tile kt (one slab): the lane's row, the lane half's 32-K block
-                const int slot = (kt >> 3) & 1;
-                sa[par] = (int)sm.mxa[slot][kt & 7][wm][2 * lr + lh];
-                sb[par] = (int)sm.mxb[slot][kt & 7][wn][2 * lr + lh];
+            if constexpr (ft::MX) {  // slab sl of K tile kt: the lane's row, the lane half's 32-K block
+                const int ks = kt * NSLAB + sl, slot = (ks >> 3) & 1;
+                sa[par] = (int)sm.mxa[slot][ks & 7][wm][2 * lr + lh];
+                sb[par] = (int)sm.mxb[slot][ks & 7][wn][2 * lr + lh];
             }
         };
         auto mf = [&](int u, int par) {
@@ -1016,10 +1020,10 @@ __device__ __forceinline__ void gemm_tile_wide(const GemmArgs& g, int64_t m0, in
                     }
                 }
                 if constexpr (ft::MX) {
-                    const int gi = t >> 3;
+                    const int gi = t / SPG;
                     if (u == 0 && gi >= 1 && gi + 1 < ng) {
-                        if ((t & 7) == 0) scn = load_group(gi + 1);
-                        if ((t & 7) == 4) store_group((gi + 1) & 1, scn);
+                        if (t % SPG == 0) scn = load_group(gi + 1);
+                        if (t % SPG == SPG / 2) store_group((gi + 1) & 1, scn);
                     }
                 }
                 mf(u, (par0 + u / TM) & 1);

@@ -19,10 +19,14 @@ tina_status tina_fail(tina_status s, const std::string& msg);
     } while (0)
 
 // Makes `dev` current for the scope of a call and restores the caller's device.
+// Kernel launch failures are read with hipGetLastError, so a status an earlier
+// call of this thread left behind (the caller's, or one of ours that ignores
+// it) is cleared first: it must not be taken for this call's.
 struct DeviceScope {
     int prev = -1, dev;
     hipError_t err = hipSuccess;
     explicit DeviceScope(int d) : dev(d) {
+        (void)hipGetLastError();
         err = hipGetDevice(&prev);
         if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
     }
