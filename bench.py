@@ -617,6 +617,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form tables")
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serving-quick", action="store_true",
+                    help="serving: only FP8 per-frame, device buffers, rho 0.5, 50 + 300 requests (for kernel traces)")
     ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored,fp32/compensated",
                     help="comma-separated precision forms of the form tables (form or form/factored)")
     ap.add_argument("--form-workloads", default="real,wide",
@@ -724,10 +726,14 @@ def main():
     if not args.no_serving:
         log("[bench] serving workload")
         o = check_oracle()
-        result["serving"] = [serving_bench(torch, prec, bud, oracle_obj=o) for prec in ("fp8", "bf16x3")
-                             for bud in (8 << 30, 256 << 20)]
-        result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho, oracle_obj=o)
-                              for rho in (0.5, 0.8) for prec in ("fp8", "bf16x3")]
+        if args.serving_quick:
+            result["serving"] = [serving_bench(torch, "fp8", 8 << 30, n_warm=50, n_meas=300, device=True,
+                                               oracle_obj=o)]
+        else:
+            result["serving"] = [serving_bench(torch, prec, bud, oracle_obj=o) for prec in ("fp8", "bf16x3")
+                                 for bud in (8 << 30, 256 << 20)]
+            result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho, oracle_obj=o)
+                                  for rho in (0.5, 0.8) for prec in ("fp8", "bf16x3")]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
