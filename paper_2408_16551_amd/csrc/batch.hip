@@ -406,8 +406,12 @@ tina_status step_graph(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, int
     return TINA_OK;
 }
 
+// tables_retired: the caller guarantees that the work of the call before the
+// previous one has completed (the server retires a step before building the
+// one after the next), so a host table's last upload is known to be done and
+// no event is recorded after it.
 tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, const Tune& tune, bool dry,
-                      const std::vector<int64_t>& frames, bool use_graph = false) {
+                      const std::vector<int64_t>& frames, bool use_graph = false, bool tables_retired = false) {
     const std::vector<GroupPlan> groups = make_groups(b, w, frames, n);
     use_graph = use_graph && groups.size() == 1;
     // Launch errors are read with hipGetLastError: a status left by an earlier
@@ -426,8 +430,10 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
         bool all_exact = true, wide = false;
         fill_table(b, w, frames, g, tune, dry, max_m, all_exact, wide);
         HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipEventRecord(b->table_free[k], s));
-        b->table_pending[k] = true;
+        if (!tables_retired || groups.size() > 1) {
+            HIP_TRY(hipEventRecord(b->table_free[k], s));
+            b->table_pending[k] = true;
+        }
         tina_pfb_batch_s::StepGraph* sg = nullptr;
         if (use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid) {
             tina_status st = step_graph(b, s, tune, max_m, all_exact, wide, sg);
@@ -500,7 +506,8 @@ void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
 }
 
 // Used by the server: run one step's items, through the cached step graph
-// when use_graph is set.
+// when use_graph is set.  The server builds a step only after retiring the
+// step before the previous one (at most two in flight).
 tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph) {
     std::vector<int64_t> frames;
     tina_status st = validate(b, w, n, frames);
@@ -513,7 +520,7 @@ tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hi
         auto it = g_tune_cache.find(signature(b, w, frames, n));
         if (it != g_tune_cache.end()) tune = it->second;
     }
-    return run_batch(b, w, n, s, tune, false, frames, use_graph);
+    return run_batch(b, w, n, s, tune, false, frames, use_graph, true);
 }
 
 // Used by the server at creation: captures the step graph of every tap-ring

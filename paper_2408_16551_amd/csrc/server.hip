@@ -55,10 +55,16 @@ void destroy_reqx(ReqX* x) {
 
 ReqX* rx(sched::Request* q) { return static_cast<ReqX*>(q->user); }
 
-// A step enqueued on the compute stream and not yet retired.
+// A step enqueued on the compute stream and not yet retired.  eb is recorded
+// after its launches.  ea marks its start: recorded before them when the
+// device had nothing else in flight, otherwise the previous step's eb (handed
+// over when that step retires), so a loaded pipeline carries one marker per
+// step instead of two (each costs the device a few microseconds between
+// steps).
 struct InFlight {
     std::vector<sched::StepItem> items;
-    hipEvent_t ea = nullptr, eb = nullptr;  // around the step's launches
+    hipEvent_t ea = nullptr, eb = nullptr;
+    bool start_at_prev = false;
 };
 
 constexpr int kMaxInFlight = 2;  // steps enqueued ahead of the device
@@ -138,15 +144,16 @@ bool tina_server_s::retire(bool block) {
     hipError_t e = block ? hipEventSynchronize(f.eb) : hipEventQuery(f.eb);
     if (e == hipErrorNotReady) return false;
     float ms = 0.f;
-    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, f.ea, f.eb);
+    if (e == hipSuccess && f.ea) (void)hipEventElapsedTime(&ms, f.ea, f.eb);
     std::unique_lock<std::mutex> lk(mu);
     device_busy_ms += ms;
     std::vector<sched::Request*> ended;
     complete(sch->step_done(f.items, e == hipSuccess, TINA_ERR_DEVICE, now_us(), &ended));
     for (sched::Request* q : ended) rx(q)->fail_msg = std::string("step failed on the device: ") + hipGetErrorString(e);
     resync(ended);
-    ev_pool.push_back(f.ea);
-    ev_pool.push_back(f.eb);
+    if (f.ea) ev_pool.push_back(f.ea);
+    if (inflight.size() > 1 && inflight[1].start_at_prev) inflight[1].ea = f.eb;  // the next step starts where this ended
+    else ev_pool.push_back(f.eb);
     inflight.pop_front();
     cv_done.notify_all();
     return true;
@@ -205,10 +212,14 @@ void tina_server_s::loop() {
                 }
                 InFlight f;
                 f.items = std::move(items);
-                f.ea = take_event();
+                f.start_at_prev = !inflight.empty();
+                if (!f.start_at_prev) f.ea = take_event();
                 f.eb = take_event();
-                tina_status st = (f.ea && f.eb) ? TINA_OK : TINA_ERR_DEVICE;
-                if (st == TINA_OK && hipEventRecord(f.ea, s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+                tina_status st = ((f.ea || f.start_at_prev) && f.eb) ? TINA_OK : TINA_ERR_DEVICE;
+                if (st == TINA_OK && f.ea && hipEventRecord(f.ea, s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+                // At most one step is in flight while this one is built, so the
+                // step that last used the batch's other host table has retired:
+                // its upload is done and no event is needed to reuse the table.
                 if (st == TINA_OK)
                     st = batch_run_items(batch, works.data(), (int32_t)works.size(), s_comp, cfg.use_graph != 0);
                 if (st == TINA_OK && hipEventRecord(f.eb, s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
