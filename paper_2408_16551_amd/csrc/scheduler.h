@@ -8,7 +8,12 @@
 // `quota` frames of it, quota = frames_per_step * max(1, max_active / ready)
 // (the step workspace holds max_active requests of frames_per_step frames).
 // Steps may be in flight while later ones are built; a request is complete
-// when every step that took its samples has completed.
+// when every step that took its samples has completed.  A slot and the
+// stream's issue order are held only while a request has samples not yet
+// given to a step: once its last samples are in a step, the stream's next
+// request may be admitted and take the following step (steps run in order on
+// one device stream, so its chunk still follows the previous one), while the
+// finished request waits only for its steps to complete.
 #pragma once
 #include <stdint.h>
 
@@ -107,7 +112,8 @@ struct Stream {
     int P = 0;
     int64_t residue_submitted = 0;  // residue after every submitted request
     int64_t residue_issued = 0;     // residue after every sample given to a step
-    bool busy = false;              // a request of this stream is admitted
+    uint64_t owner = 0;             // the admitted request whose samples are not all issued (0: none)
+    uint64_t last_admitted = 0;     // the stream's most recently admitted request
     std::deque<uint64_t> queued;    // its queued requests, oldest first
 };
 
@@ -193,16 +199,18 @@ class Scheduler {
         return 1;
     }
 
-    // Admission in arrival order while a slot is free: a request of a busy
-    // stream waits (its chunks run in order), a request whose buffers do not
-    // fit the arena blocks the ones behind it (large requests do not starve).
+    // Admission in arrival order while a slot is free (fewer than max_active
+    // requests with samples to issue): a request whose stream still issues an
+    // earlier request waits (its chunks run in order), a request whose
+    // buffers do not fit the arena blocks the ones behind it (large requests
+    // do not starve).
     std::vector<Request*> admit(double t) {
         std::vector<Request*> out;
         for (auto it = queue_.begin(); it != queue_.end();) {
             Request* q = find(*it);
             Stream& st = streams_[q->stream];
-            if (st.busy || st.queued.empty() || st.queued.front() != q->id) { ++it; continue; }
-            if ((int)active_.size() >= max_active_) break;
+            if (st.owner != 0 || st.queued.empty() || st.queued.front() != q->id) { ++it; continue; }
+            if (n_issuing_ >= max_active_) break;
             if (!q->device) {
                 const int64_t oi = arena_.alloc(q->in_bytes);
                 const int64_t oo = oi >= 0 ? arena_.alloc(q->out_bytes) : -1;
@@ -217,7 +225,9 @@ class Scheduler {
             q->phase = ACTIVE;
             q->t_admit = t;
             q->residue0 = st.residue_issued;
-            st.busy = true;
+            st.owner = q->id;
+            st.last_admitted = q->id;
+            ++n_issuing_;
             st.queued.pop_front();
             active_.push_back(q);
             out.push_back(q);
@@ -228,6 +238,7 @@ class Scheduler {
     }
 
     const std::vector<Request*>& active() const { return active_; }
+    int issuing() const { return n_issuing_; }  // active requests with samples not yet issued
 
     // The next step: every active request whose input is on the device and
     // that has samples not yet given to a step takes up to `quota` frames;
@@ -250,6 +261,7 @@ class Scheduler {
             q->frames_issued += frames;
             st.residue_issued = (r + s) % st.P;
             if (q->steps++ == 0) q->t_first_step = t;
+            if (q->samples_issued == q->n_samples) release_issue(q);
         }
         ++stats_.steps;
         return items;
@@ -262,14 +274,30 @@ class Scheduler {
     std::vector<Request*> step_done(const std::vector<StepItem>& items, bool ok, int status, double t,
                                     std::vector<Request*>* ended = nullptr) {
         std::vector<Request*> complete;
+        if (!ok) {
+            // The step's requests end, and with them every later request of
+            // their streams already admitted (its chunks would follow output
+            // this step did not produce).
+            std::vector<int> failed;
+            for (const StepItem& it : items) {
+                Request* q = find(it.id);  // a request that ended early may be gone
+                if (!q || q->phase != ACTIVE) continue;
+                failed.push_back(q->stream);
+                end_active(q, status, t);
+                if (ended) ended->push_back(q);
+            }
+            std::vector<Request*> later;
+            for (Request* q : active_)
+                if (std::find(failed.begin(), failed.end(), q->stream) != failed.end()) later.push_back(q);
+            for (Request* q : later) {
+                end_active(q, status, t);
+                if (ended) ended->push_back(q);
+            }
+            return complete;
+        }
         for (const StepItem& it : items) {
             Request* q = find(it.id);  // a request that ended early may be gone
             if (!q || q->phase != ACTIVE) continue;
-            if (!ok) {
-                end_active(q, status, t);
-                if (ended) ended->push_back(q);
-                continue;
-            }
             q->samples_done += it.n_samples;
             q->frames_done += it.frames;
             stats_.samples += it.n_samples;
@@ -281,11 +309,17 @@ class Scheduler {
     }
 
     // Admitted requests with nothing to process (zero samples) whose input
-    // event has passed: complete at once.
+    // event has passed: complete at once, after any earlier request of their
+    // stream.
     std::vector<Request*> take_empty() {
         std::vector<Request*> out;
+        auto older_active = [&](const Request* q) {  // a stream's requests complete in order
+            for (const Request* o : active_)
+                if (o->stream == q->stream && o->id < q->id) return true;
+            return false;
+        };
         for (Request* q : active_)
-            if (q->in_ready && q->n_samples == 0) out.push_back(q);
+            if (q->in_ready && q->n_samples == 0 && !older_active(q)) out.push_back(q);
         for (Request* q : out) to_draining(q);
         return out;
     }
@@ -325,10 +359,17 @@ class Scheduler {
     const std::deque<uint64_t>& queue() const { return queue_; }
 
   private:
+    void release_issue(Request* q) {
+        Stream& st = streams_[q->stream];
+        if (st.owner == q->id) {
+            st.owner = 0;
+            --n_issuing_;
+        }
+    }
     void remove_active(Request* q) {
         auto it = std::find(active_.begin(), active_.end(), q);
         if (it != active_.end()) active_.erase(it);
-        streams_[q->stream].busy = false;
+        release_issue(q);
     }
     void release_buffers(Request* q) {
         if (q->off_in >= 0) arena_.release(q->off_in);
@@ -342,9 +383,10 @@ class Scheduler {
     void end_active(Request* q, int status, double t) {
         // The stream continues as if the whole request had been processed,
         // so that later requests complete the frames counted at their submit
-        // (the driver resets the stream's state to this residue).
+        // (the driver resets the stream's state to this residue).  A request
+        // admitted after it already continues from there.
         Stream& st = streams_[q->stream];
-        st.residue_issued = (q->residue0 + q->n_samples) % st.P;
+        if (st.last_admitted == q->id) st.residue_issued = (q->residue0 + q->n_samples) % st.P;
         remove_active(q);
         release_buffers(q);
         q->status = status;
@@ -353,6 +395,7 @@ class Scheduler {
     }
 
     int max_active_, max_queued_;
+    int n_issuing_ = 0;
     int64_t fps_;
     uint64_t next_id_ = 1;
     Arena arena_;

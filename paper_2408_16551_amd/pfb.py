@@ -531,6 +531,25 @@ class Server:
         self._lent.pop(rid, None)
         return self._res(r)
 
+    def submit_ptr(self, sid: int, in_ptr: int, n_samples: int, out_ptr: int, out_frames: int, device: bool,
+                   ready_stream: int = 0) -> int:
+        """submit() without the array checks, for a caller that owns and has
+        checked its buffers (a load generator): raw pointers (device pointers
+        when device is set, then ready_stream is the stream writing the input),
+        the input's sample count and the output's capacity in frames.  The
+        caller keeps both buffers alive until the request is collected."""
+        r = _Request()
+        r.stream_id = int(sid)
+        r.flags = 1 if device else 0
+        r.host_in = in_ptr or None
+        r.n_samples = int(n_samples)
+        r.host_out = out_ptr or None
+        r.out_capacity_frames = int(out_frames)
+        r.ready_stream = ready_stream or None
+        rid = ctypes.c_uint64()
+        check(load().tina_pfb_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
     def wait(self, rid: int, timeout_s: float = -1.0):
         r = _Result()
         us = -1 if timeout_s < 0 else int(timeout_s * 1e6)

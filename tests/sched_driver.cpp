@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <deque>
 #include <mutex>
 #include <random>
@@ -31,17 +32,27 @@ struct Scenario {
     unsigned seed;
 };
 
+// Slots: at most max_active requests with samples to issue, at most one per
+// stream, and it is the stream's newest admitted request; the stream's older
+// active requests are fully issued and wait for their steps.
 static void check_invariants(Scheduler& s, int max_active) {
-    REQUIRE((int)s.active().size() <= max_active);
     REQUIRE(s.arena().used() <= s.arena().capacity());
+    int issuing = 0;
     std::vector<int> per_stream(s.n_streams(), 0);
+    std::vector<uint64_t> newest(s.n_streams(), 0);
+    for (Request* q : s.active()) newest[q->stream] = std::max(newest[q->stream], q->id);
     for (Request* q : s.active()) {
         REQUIRE(q->phase == ACTIVE);
-        REQUIRE(s.stream(q->stream).busy);
-        REQUIRE(++per_stream[q->stream] == 1);
         REQUIRE(q->samples_done <= q->samples_issued && q->samples_issued <= q->n_samples);
         REQUIRE(q->frames_done <= q->frames_issued && q->frames_issued <= q->frames_total);
+        if (q->samples_issued < q->n_samples) {
+            ++issuing;
+            REQUIRE(++per_stream[q->stream] == 1);
+            REQUIRE(q->id == newest[q->stream]);
+            REQUIRE(s.stream(q->stream).owner == q->id);
+        }
     }
+    REQUIRE(issuing <= s.issuing() && s.issuing() <= max_active);
 }
 
 static void run(const Scenario& sc) {
@@ -71,6 +82,7 @@ static void run(const Scenario& sc) {
     });
 
     std::deque<std::vector<StepItem>> inflight;
+    std::vector<uint64_t> last_done(sc.n_streams, 0);
     std::vector<Request*> draining;
     for (int it = 0;; ++it) {
         std::lock_guard<std::mutex> lk(mu);
@@ -99,6 +111,8 @@ static void run(const Scenario& sc) {
         }
         for (Request* q : draining) {
             REQUIRE(q->frames_done == q->frames_total);
+            REQUIRE(q->id > last_done[q->stream]);  // a stream's requests complete in order
+            last_done[q->stream] = q->id;
             s.finish(q, 0, it);
         }
         draining.clear();

@@ -185,3 +185,50 @@ def test_scheduler_under_sanitizers(sanitizer, tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "scenarios ok" in r.stdout
+
+
+def test_next_request_of_a_stream_is_admitted_once_the_previous_is_issued():
+    # R1's samples all go to step 1; R2 of the same stream is admitted at once
+    # and takes step 2 while step 1 is still in flight; both complete in order.
+    P, fps = 16, 4
+    ops = [("add_stream", P, 0), ("submit", 0, P * 4), ("submit", 0, P * 4)]
+    ops += [("admit", 0, 0), ("ready", 0, 1), ("step", 0, 0), ("admit", 0, 0), ("ready", 0, 2), ("step", 0, 0)]
+    ev = sim(ops, max_active=1, frames_per_step=fps)
+    assert [e["id"] for e in of(ev, "admit")] == [1, 2]
+    assert step_items(ev) == [[(1, P * 4, 4)], [(2, P * 4, 4)]]
+    assert not [e for e in of(ev, "complete") if e["id"]]
+    ev = sim(ops + [("complete", 0, 0), ("complete", 0, 0)], max_active=1, frames_per_step=fps)
+    assert [e["id"] for e in of(ev, "complete") if e["id"]] == [1, 2]
+
+
+def test_a_request_still_issuing_holds_its_slot_and_stream():
+    # R1 needs two steps: until its last samples are issued, R2 (same stream)
+    # and R3 (another stream, no free slot) wait.
+    P, fps = 16, 4
+    ops = [("add_stream", P, 0), ("add_stream", P, 0), ("submit", 0, P * 8), ("submit", 0, P), ("submit", 1, P)]
+    ops += [("admit", 0, 0), ("ready", 0, 1), ("step", 0, 0), ("admit", 0, 0)]
+    ev = sim(ops, max_active=1, frames_per_step=fps)
+    assert [e["id"] for e in of(ev, "admit")] == [1]
+    ev = sim(ops + [("step", 0, 0), ("admit", 0, 0)], max_active=1, frames_per_step=fps)
+    assert [e["id"] for e in of(ev, "admit")] == [1, 2]
+
+
+def test_failed_step_ends_the_later_requests_of_its_streams():
+    P, fps = 16, 4
+    ops = [("add_stream", P, 0), ("add_stream", P, 0), ("submit", 0, P * 4), ("submit", 0, P * 4), ("submit", 1, P * 4)]
+    ops += [("admit", 0, 0), ("ready", 0, 1), ("ready", 0, 3), ("step", 0, 0)]        # step 1: R1 and R3
+    ops += [("admit", 0, 0), ("ready", 0, 2), ("step", 0, 0)]                         # step 2: R2
+    ops += [("complete", 4, 0), ("complete", 0, 0)]                                   # step 1 fails
+    ev = sim(ops, max_active=2, frames_per_step=fps)
+    done = {e["id"]: e["status"] for e in of(ev, "complete") if e["id"]}
+    assert done == {1: 4, 3: 4, 2: 4}
+
+
+def test_empty_request_completes_after_the_earlier_request_of_its_stream():
+    P = 16
+    ops = [("add_stream", P, 0), ("submit", 0, P * 4), ("submit", 0, 0)]
+    ops += [("admit", 0, 0), ("ready", 0, 1), ("step", 0, 0), ("admit", 0, 0), ("ready", 0, 2), ("step", 0, 0)]
+    ev = sim(ops, max_active=2, frames_per_step=4)
+    assert not [e for e in of(ev, "complete") if e["id"]]
+    ev = sim(ops + [("complete", 0, 0), ("step", 0, 0)], max_active=2, frames_per_step=4)
+    assert [e["id"] for e in of(ev, "complete") if e["id"]] == [1, 2]
