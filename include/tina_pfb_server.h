@@ -11,7 +11,12 @@
  * A server thread runs steps back to back, building and enqueuing the next
  * step while the previous one is still on the device.  Requests queue in arrival order
  * and are admitted while a slot is free and their device buffers (input and
- * output) fit the HBM budget; a stream runs one request at a time, in order.
+ * output) fit the HBM budget.  A request holds its slot, and its stream's
+ * turn, until its last samples are in a step: the stream's next request may
+ * then take the following step while the earlier one waits for its steps to
+ * complete.  A stream's chunks are processed, and its requests complete, in
+ * order.  A step that fails ends its requests and every later admitted
+ * request of their streams.
  * Each step gives every admitted request whose input has reached the device
  * up to `frames_per_step` frames of work (times max_active / ready requests,
  * rounded down, when fewer than max_active are ready: the step workspace is
@@ -152,8 +157,9 @@ tina_status tina_server_arena_simulate(int64_t capacity, const int64_t* ops, int
 /* Host-only run of the server's scheduler on a scripted sequence of
  * operations, exposed for tests; no device work.  The decisions are those of
  * the running server: admission in arrival order while a slot is free and the
- * buffers fit the arena (a stream runs one request at a time; a request that
- * does not fit blocks the ones behind it), per-step quotas (frames_per_step
+ * buffers fit the arena (a slot and the stream's turn are held until the
+ * request's last samples are in a step; a request that does not fit blocks
+ * the ones behind it), per-step quotas (frames_per_step
  * times max(1, max_active / ready requests) frames per request), cancellation
  * of the newest queued request of a stream, steps completing or failing in
  * order.  Requests are complex64 (8 bytes per sample and per output value).
