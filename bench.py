@@ -296,7 +296,45 @@ def ops_bench(torch, steps=10):
         res[f"fir_k{K}_r32"] = {"ms": round(sec * 1e3, 4), "gsps": round(n / sec / 1e9, 2),
                                 "tflops": round(2.0 * K * n / sec / 1e12, 2)}
         f.close()
+    res["library_gemm"] = library_gemm(torch)
     log(f"[bench] ops: {res}")
+    return res
+
+
+def library_gemm(torch, reps=10):
+    """Context for the DFT kernels: the ROCm library GEMM (torch.matmul, and
+    torch._scaled_mm for FP8) on the DFT GEMM shapes of the two form
+    workloads -- frames x K by K x N -- with random operands.  Not part of
+    the filter bank; its output type is the input type (bf16) or FP32 (FP8)."""
+    def t(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    res = {}
+    for name, (M, K, N) in (("real_1024", (65536, 1024, 1024)), ("complex_4096", (16384, 8192, 8192))):
+        a = torch.randn(M, K, device="cuda").to(torch.bfloat16)
+        b = torch.randn(N, K, device="cuda").to(torch.bfloat16)
+        bt = b.t().contiguous()   # K x N, row-major
+        ms = t(lambda: torch.matmul(a, bt))
+        res[f"bf16_{name}"] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 1),
+                               "frac": round(2.0 * M * N * K / ms / 1e9 / PEAK_TFLOPS["bf16"], 4)}
+        try:
+            a8, b8 = a.to(torch.float8_e4m3fn), b.to(torch.float8_e4m3fn)
+            one = torch.ones((), device="cuda")
+            b8t = b8.t()   # K x N column-major, the layout _scaled_mm takes for its second operand
+            ms = t(lambda: torch._scaled_mm(a8, b8t, scale_a=one, scale_b=one, out_dtype=torch.float32))
+            res[f"fp8_{name}"] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 1),
+                                  "frac": round(2.0 * M * N * K / ms / 1e9 / PEAK_TFLOPS["fp8"], 4)}
+        except Exception as e:  # the FP8 library path is optional context
+            res[f"fp8_{name}"] = {"error": repr(e)[:120]}
+        del a, b, bt
     return res
 
 
