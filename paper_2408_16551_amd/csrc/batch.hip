@@ -108,6 +108,7 @@ struct tina_pfb_batch_s {
     };
     std::map<std::string, StepGraph> graphs;
     int64_t graph_gemm_grid = 0;  // GEMM grid the step graphs are captured with (0: no graphs)
+    bool frame_stage = true;      // long per-frame scaled items run the single-pass frame stage
     StreamOrder order;            // every call shares ws, amax, fexp and d_table
 
     void release() {
@@ -203,6 +204,8 @@ tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vect
     return TINA_OK;
 }
 
+constexpr int64_t kFrameStageMinFrames = 2048;
+
 // Fills the host table for items [g.first, g.first + g.count) and returns the
 // launch parameters.  `dry` leaves state updates out (tuning runs).
 void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, const GroupPlan& g,
@@ -227,9 +230,9 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         return tune.fir_tf_mult * ring < 16 ? ((16 + ring - 1) / ring) * ring : tune.fir_tf_mult * ring;
     };
 
-    std::vector<int64_t> fu(g.count), gu(g.count), su(g.count);
-    std::vector<double> fc(g.count), gc(g.count), sc(g.count, 1.0);
-    int64_t ws_off = 0, amax_off = 0, f0 = 0, g0 = 0, s0 = 0;
+    std::vector<int64_t> fu(g.count), gu(g.count), su(g.count), ru(g.count);
+    std::vector<double> fc(g.count), gc(g.count), sc(g.count, 1.0), rc(g.count, 1.0);
+    int64_t ws_off = 0, amax_off = 0, f0 = 0, g0 = 0, s0 = 0, r0 = 0;
     for (int i = 0; i < g.count; ++i) {
         tina_pfb_work& it = w[g.first + i];
         tina_pfb_plan_s* p = it.plan;
@@ -285,12 +288,32 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.Aq1 = fa.q1;
         ga.Aqs = fa.qs;
         ga.fexp = fa.fexp;
-        const int ring = (!all_exact && MT <= 16) ? p->M : MT;
-        const int TF = frames_per_thread(ring);
-        bi.fir_tf = TF;
-        const int64_t runs = (F + TF - 1) / TF;
-        fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
-        fc[i] = (double)TF * ring;
+        // Per-frame scaled items with frame rows of 1024 threads and at least
+        // kFrameStageMinFrames frames run in one pass (frame stage, units of
+        // fir_frame_batch_tf(M) frames); the others in the three FIR launches
+        // (units of 256 threads).  A frame-stage unit walks its frames one
+        // ring block after another, so short items would take a unit's whole
+        // latency (~70 us measured in serving steps) for little work.
+        bi.fir_single = (b->frame_stage && form_scaled(b->form) && F >= kFrameStageMinFrames &&
+                         fir_frame_batch_vec(fa) != 0) ? 1 : 0;
+        bi.frame_unit0 = r0;
+        if (bi.fir_single) {
+            const int TF = fir_frame_batch_tf(p->M);
+            bi.fir_tf = TF;
+            fu[i] = 0;
+            fc[i] = 1.0;
+            ru[i] = F > 0 ? (F + TF - 1) / TF : 0;
+            rc[i] = (double)TF * p->W * p->M;
+        } else {
+            const int ring = (!all_exact && MT <= 16) ? p->M : MT;
+            const int TF = frames_per_thread(ring);
+            bi.fir_tf = TF;
+            const int64_t runs = (F + TF - 1) / TF;
+            fu[i] = F > 0 ? (runs * p->W + 255) / 256 : 0;
+            fc[i] = (double)TF * ring;
+            ru[i] = 0;
+        }
+        r0 += ru[i];
         gu[i] = F > 0 ? ((F + tile_m - 1) / tile_m) * ((p->N + tile_n - 1) / tile_n) : 0;
         gc[i] = (double)p->K;
         bi.fir_unit0 = f0;
@@ -314,7 +337,9 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
     t->fir_units = f0;
     t->gemm_units = g0;
     t->st_units = s0;
+    t->frame_units = r0;
     split_by_cost(fu, fc, t->fir_bounds);
+    split_by_cost(ru, rc, t->frame_bounds);
     split_by_cost(gu, gc, t->gemm_bounds);
     split_by_cost(su, sc, t->st_bounds);
 }
@@ -354,8 +379,8 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
     const int grid_fir = b->cus * 4;
     const int64_t grid_gemm = fixed_gemm_grid > 0 ? fixed_gemm_grid : gemm_grid(b->h_table);
     const int qmode = form_fir_qmode(b->form);
-    if (always || b->h_table->fir_units > 0)
-        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, qmode, grid_fir, s));
+    if (always || b->h_table->fir_units > 0 || b->h_table->frame_units > 0)
+        HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, qmode, grid_fir, s, b->frame_stage));
     if (always || b->h_table->gemm_units > 0)
         HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s, wide));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
@@ -504,6 +529,11 @@ void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
     while (g == (int64_t)b->cus * 4 || g == (int64_t)b->cus * 2) g += 8;  // unlike every other stage's grid
     b->graph_gemm_grid = g;
 }
+
+// Used by the server: steps keep every per-frame scaled item in the three FIR
+// launches (a step's items are short; a frame-stage unit's latency would set
+// the step's length).
+void batch_disable_frame_stage(tina_pfb_batch_s* b) { b->frame_stage = false; }
 
 // Used by the server: run one step's items, through the cached step graph
 // when use_graph is set.  The server builds a step only after retiring the

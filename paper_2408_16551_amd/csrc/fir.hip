@@ -105,12 +105,14 @@ __global__ __launch_bounds__(256) void frame_exponent_kernel(const float* __rest
     if (f < F) frame_exponent_wave(amax, nparts, f, limit, fexp);  // wave-uniform
 }
 
-// The same for every item of a batch: the grid's waves share each item's
-// frames, item after item.
+// The same for every item of a batch that takes the three launches (items
+// of the single-pass frame stage derive their exponents themselves): the
+// grid's waves share each item's frames, item after item.
 __global__ __launch_bounds__(256) void frame_exponent_batch_kernel(const BatchTable* __restrict__ t, float limit) {
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     for (int it = 0; it < t->n_items; ++it) {
+        if (t->items[it].fir_single) continue;
         const FirArgs& a = t->items[it].fir;
         for (int64_t f = w; f < a.F; f += nw) frame_exponent_wave(a.amax, a.nparts, f, limit, a.fexp);
     }
@@ -176,9 +178,15 @@ hipError_t launch_fir(FirArgs& a, hipStream_t s) {
     return launch_fir_mode_f32(a, vec, s);
 }
 
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s) {
-    if (qmode_frame_scaled(qmode)) {  // as in launch_fir: maxima, exponents, codes
-        hipError_t e = launch_fir_batch_mode_amaxonly(t, max_m, all_exact, grid, s);
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s,
+                            bool frame_stage) {
+    if (qmode_frame_scaled(qmode)) {
+        // Items with whole frame rows of 1024 threads: one pass (frame stage);
+        // the others as in launch_fir: maxima, exponents, codes.
+        hipError_t e = hipSuccess;
+        if (frame_stage) e = launch_fir_frame_batch(t, qmode, grid / 4, s);  // one 1024-thread block per CU
+        if (e != hipSuccess) return e;
+        e = launch_fir_batch_mode_amaxonly(t, max_m, all_exact, grid, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(frame_exponent_batch_kernel, dim3(grid), dim3(256), 0, s, t,
                            qmode == QM_FP8F ? 448.0f : 32768.0f);

@@ -18,14 +18,15 @@ namespace {
 
 constexpr int kFrameMaxThreads = 1024;
 
+// One block's run of frames [run * TF, ...) of a, with blockDim.x = W / VEC.
+// smax: [wave][frame of the ring block] (stride MT), sexp: the ring block's
+// frame exponents.  Every thread of the block takes the same barriers.
 template <int VEC, int MT, bool EXACT, int QM>
-__global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_kernel(FirArgs a, int TF) {
+__device__ __forceinline__ void frame_unit(const FirArgs& a, int TF, int64_t run, float* smax, int* sexp) {
     using V = typename VecT<VEC>::T;
-    __shared__ float smax[kFrameMaxThreads / 64][MT];  // [wave][frame of the ring block]
-    __shared__ int sexp[MT];                            // the ring block's frame exponents
     const int col = threadIdx.x, j0 = col * VEC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int64_t f_begin = (int64_t)blockIdx.x * TF;
+    const int64_t f_begin = run * TF;
     const int64_t f_end = min(a.F, f_begin + TF);
     const int M = EXACT ? MT : a.M;
     const float limit = QM == QM_FP8F ? 448.0f : 32768.0f;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_kernel(FirArgs a, 
                 for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fabsf(vget<VEC>(ys[u], v)));
                 mx = group_absmax<32>(mx);
                 mx = fmaxf(mx, __shfl_xor(mx, 32));
-                if (lane == 0) smax[wave][u] = mx;
+                if (lane == 0) smax[wave * MT + u] = mx;
             }
         }
         __syncthreads();  // smax complete
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_kernel(FirArgs a, 
         // its exponent once for the block.
         if (threadIdx.x < MT && (int)threadIdx.x < nu) {
             float fm = 0.0f;
-            for (int w = 0; w < nwaves; ++w) fm = fmaxf(fm, smax[w][threadIdx.x]);
+            for (int w = 0; w < nwaves; ++w) fm = fmaxf(fm, smax[w * MT + threadIdx.x]);
             const int e = frame_exponent(fm, limit);
             sexp[threadIdx.x] = e;
             a.fexp[fb + threadIdx.x] = e;
@@ -96,6 +97,46 @@ __global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_kernel(FirArgs a, 
         // The next block writes smax only after this block's reads of it
         // (the barrier above) and sexp only after its first barrier, which
         // every thread reaches once done with these stores.
+    }
+}
+
+template <int VEC, int MT, bool EXACT, int QM>
+__global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_kernel(FirArgs a, int TF) {
+    __shared__ float smax[kFrameMaxThreads / 64 * MT];
+    __shared__ int sexp[MT];
+    frame_unit<VEC, MT, EXACT, QM>(a, TF, blockIdx.x, smax, sexp);
+}
+
+// Batched: every item whose frame row is exactly 1024 threads of VEC floats
+// (W = 1024, 2048 or 4096) and whose tap count has an exact ring here
+// (fir_frame_batch_vec) runs its frame runs as units of this persistent
+// kernel, each XCD's blocks walking that XCD's cost-balanced range; the
+// other items of a per-frame scaled batch take the three launches.  The ring
+// is unrolled for the item's own M, as in the streaming batched FIR.
+template <int VEC, int M0, int MMAX, int QM>
+__device__ __forceinline__ void frame_unit_own_m(const FirArgs& a, int TF, int64_t run, float* smax, int* sexp) {
+    if constexpr (M0 <= MMAX) {
+        if (a.M == M0) frame_unit<VEC, M0, true, QM>(a, TF, run, smax, sexp);
+        else frame_unit_own_m<VEC, M0 + 1, MMAX, QM>(a, TF, run, smax, sexp);
+    }
+}
+
+template <int QM>
+__global__ __launch_bounds__(kFrameMaxThreads) void fir_frame_batch_kernel(const BatchTable* __restrict__ t) {
+    __shared__ float smax[kFrameMaxThreads / 64 * 16];
+    __shared__ int sexp[16];
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t end = t->frame_bounds[x + 1];
+    for (int64_t u = t->frame_bounds[x] + i; u < end; u += nbx) {
+        const int it = batch_find(t->items, t->n_items, u, /*stage=*/3);
+        const BatchItem& b = t->items[it];
+        const FirArgs fa = b.fir;  // a private copy (see fir_batch_kernel)
+        const int64_t run = u - b.frame_unit0;
+        switch (fa.W) {  // uniform over the block: one item per unit
+            case 1024: frame_unit_own_m<1, 1, 16, QM>(fa, b.fir_tf, run, smax, sexp); break;
+            case 2048: frame_unit_own_m<2, 1, 16, QM>(fa, b.fir_tf, run, smax, sexp); break;
+            default: frame_unit_own_m<4, 1, 8, QM>(fa, b.fir_tf, run, smax, sexp); break;
+        }
     }
 }
 
@@ -161,6 +202,32 @@ int fir_frame_vec(const FirArgs& a) {
         return 0;
     }
     return vec;
+}
+
+int fir_frame_batch_vec(const FirArgs& a) {
+    if (!qmode_frame_scaled(a.qmode)) return 0;
+    const int vec = a.W == 1024 ? 1 : (a.W == 2048 ? 2 : (a.W == 4096 ? 4 : 0));
+    if (vec == 0 || a.M < 1 || a.M > (vec == 4 ? 8 : 16)) return 0;
+    auto aligned = [](const void* p, int bytes) { return ((uintptr_t)p % bytes) == 0; };
+    if (a.plen % vec != 0 || !aligned(a.chunk, 4 * vec) || (a.prefix && !aligned(a.prefix, 4 * vec))) return 0;
+    if (a.qmode == QM_FP8F) {
+        if (!aligned(a.q, 4) || a.ldq % 4 != 0) return 0;
+    } else if (!aligned(a.q, 2 * vec) || (a.q1 && !aligned(a.q1, 2 * vec)) || a.ldq % vec != 0) {
+        return 0;
+    }
+    return vec;
+}
+
+int fir_frame_batch_tf(int M) { return M * ((128 + M - 1) / M); }
+
+hipError_t launch_fir_frame_batch(const BatchTable* t, int qmode, int grid, hipStream_t s) {
+    switch (qmode) {
+        case QM_FP8F: hipLaunchKernelGGL(fir_frame_batch_kernel<QM_FP8F>, dim3(grid), dim3(kFrameMaxThreads), 0, s, t); break;
+        case QM_FP16F: hipLaunchKernelGGL(fir_frame_batch_kernel<QM_FP16F>, dim3(grid), dim3(kFrameMaxThreads), 0, s, t); break;
+        case QM_FP16FX2: hipLaunchKernelGGL(fir_frame_batch_kernel<QM_FP16FX2>, dim3(grid), dim3(kFrameMaxThreads), 0, s, t); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fir_frame(const FirArgs& a, hipStream_t s) {

@@ -141,8 +141,9 @@ struct BatchItem {
     int64_t fir_unit0;      // first FIR unit (256-thread block) of this item
     int64_t gemm_unit0;     // first GEMM tile of this item
     int64_t st_unit0;       // first state-update unit
-    int32_t fir_tf;         // frames per FIR thread
-    int32_t pad_;
+    int32_t fir_tf;         // frames per FIR thread (fir_single: frames per frame-stage unit)
+    int32_t fir_single;     // per-frame scaled form: one pass, whole frame rows per unit (frame stage)
+    int64_t frame_unit0;    // first unit of the frame stage
     float* st_dst;          // state buffer to fill (nullptr: no state)
     int64_t st_start, st_count;
 };
@@ -152,20 +153,24 @@ struct BatchItem {
 struct BatchTable {
     int32_t n_items;
     int32_t pad_;
-    int64_t fir_units, gemm_units, st_units;
-    int64_t fir_bounds[9], gemm_bounds[9], st_bounds[9];
+    int64_t fir_units, gemm_units, st_units, frame_units;
+    int64_t fir_bounds[9], gemm_bounds[9], st_bounds[9], frame_bounds[9];
     int32_t gemm_bn;        // GEMM tile columns of this launch (kGemmBN or 2 * kGemmBN, or the wide tile's)
     int32_t gemm_wide;      // the launch uses the wide raw-operand tiles
     BatchItem items[1];     // n_items entries follow
 };
 
-// Index of the item that owns unit u of a stage (0 FIR, 1 GEMM, 2 state):
+// Index of the item that owns unit u of a stage (0 FIR, 1 GEMM, 2 state,
+// 3 single-pass per-frame FIR):
 // the last item whose first unit is <= u.
 __device__ inline int batch_find(const BatchItem* items, int n, int64_t u, int stage) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t s = stage == 0 ? items[mid].fir_unit0 : (stage == 1 ? items[mid].gemm_unit0 : items[mid].st_unit0);
+        const int64_t s = stage == 0 ? items[mid].fir_unit0
+                          : stage == 1 ? items[mid].gemm_unit0
+                          : stage == 2 ? items[mid].st_unit0
+                                       : items[mid].frame_unit0;
         if (s <= u) lo = mid;
         else hi = mid - 1;
     }
@@ -177,7 +182,14 @@ constexpr int kGemmBM = 128, kGemmBN = 128;
 
 // Per-frame scaled qmodes run three launches: partial maxima, per-frame
 // exponents, scaled codes.
-hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s);
+// frame_stage: per-frame scaled forms also launch the single-pass frame stage
+// (the items flagged fir_single).
+hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s,
+                            bool frame_stage);
+// Per-frame scaled items a batch runs in one pass (whole frame rows of 1024
+// threads): the floats per thread, or 0 (three launches); frames per unit.
+int fir_frame_batch_vec(const FirArgs& a);
+int fir_frame_batch_tf(int M);
 // FirArgs::qmode the FIR writes for a DFT form (0: FP32 y): every form but
 // FP32 takes its operand straight from the FIR.
 inline int form_fir_qmode(int form) {

@@ -150,5 +150,6 @@ struct tina_pfb_work;
 tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph);
 // Bound on the GEMM tiles of one step (fixes the grid of captured steps).
 void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles);
+void batch_disable_frame_stage(tina_pfb_batch_s* b);
 // Captures every step-graph variant in advance (needs the bound above).
 tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s);

@@ -294,6 +294,7 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
     // Largest GEMM tile count of a step: every slot with frames_per_step
     // frames of the widest stream (128 x 128 tiles, N = 2 * max_channels).
+    batch_disable_frame_stage(sv->batch);
     batch_set_graph_bound(sv->batch, (int64_t)c->max_active * ((c->frames_per_step + kGemmBM - 1) / kGemmBM) *
                                          ((2 * (int64_t)c->max_channels + kGemmBN - 1) / kGemmBN));
     if (hipStreamCreateWithFlags(&sv->s_comp, hipStreamNonBlocking) != hipSuccess ||

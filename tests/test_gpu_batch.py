@@ -57,6 +57,28 @@ def test_batch_equals_single_execute_bitwise(precision):
         assert torch.equal(o[:f], single)
 
 
+# Per-frame scaled forms with long items: those with 1024-, 2048- or 4096-float
+# frames run the single-pass frame stage (1, 2 and 4 floats per thread), the
+# 256-channel complex item the three FIR launches; all equal the single path.
+LONG_MIX = [(512, 16, True, 512 * 3000 + 5), (1024, 9, False, 1024 * 2500), (2048, 8, True, 2048 * 2100 + 3),
+            (256, 16, True, 256 * 2500), (1024, 13, True, 1024 * 2049)]
+
+
+@pytest.mark.parametrize("precision", ["fp8", "fp16", "fp16x3"])
+def test_batch_frame_stage_equals_single_execute_bitwise(precision):
+    from paper_2408_16551_amd.pfb import Batch
+    plans, xs, outs = _items(LONG_MIX, precision, seed=11)
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    b = Batch(precision, max_items=8, workspace_bytes=1 << 30)
+    fw = b.execute([(p, x, o) for p, x, o in zip(plans, xd, outs)])
+    torch.cuda.synchronize()
+    for p, x, o, f in zip(plans, xd, outs, fw):
+        single = p(x)
+        torch.cuda.synchronize()
+        assert f == single.shape[0]
+        assert torch.equal(o[:f], single)
+
+
 # Largest tap count 8 with mixed counts: every item runs the ring unrolled for
 # its own M (1..8), which must give the single path's bits and the oracle's values.
 SMALL_M_MIX = [(64, 3, True, 64 * 90 + 7), (128, 5, False, 128 * 70), (256, 7, True, 256 * 41 + 3),
@@ -121,10 +143,15 @@ def test_batch_item_larger_than_workspace_is_rejected():
     assert e.value.status == 7
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp8", "fp16x3"])
 def test_batch_with_states_chunked_equals_one_shot(precision):
+    # Per-frame scaled forms: items with 1024- or 2048-float frames and at
+    # least 2048 frames in a call run the single-pass frame stage (here the
+    # 512-channel complex and 1024-channel real items in the larger chunks),
+    # the others the three FIR launches.
     from paper_2408_16551_amd.pfb import Batch, State
-    mix = [(256, 16, True, 256 * 40 + 77), (512, 11, True, 512 * 30 + 3), (1024, 16, False, 1024 * 25 + 500)]
+    mix = [(256, 16, True, 256 * 40 + 77), (512, 11, True, 512 * 6000 + 3), (1024, 16, False, 1024 * 5000 + 500),
+           (1024, 13, True, 1024 * 19 + 9)]
     plans, xs, _ = _items(mix, precision, seed=3)
     b = Batch(precision, max_items=8)
     states = [State(p) for p in plans]
