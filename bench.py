@@ -500,13 +500,15 @@ def serving_check(torch, sv, pool, device, oracle_obj, seed, n_req=16):
 
 
 def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005, device=False,
-                  frames_per_step=1024, oracle_obj=None, max_active=64):
+                  frames_per_step=1024, oracle_obj=None, max_active=64, use_graph=False):
     """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
     1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
     random stream, length log-uniform 2^16-2^22.  The server runs up to
     max_active requests with samples to issue, frames_per_step frames each per
     step (64 x 1024: at 0.8 of the capacity p99 was 1.6-1.9 ms against 3.5 ms
-    with 32 slots; 128 slots or 2048 frames measured no better).  The rate is rho times the
+    with 32 slots; 128 slots or 2048 frames measured no better).  Steps are
+    plain launches: a graph replay leaves the device idle ~8 us longer per
+    step and measured no lower latency.  The rate is rho times the
     batched path's capacity C on the same mix with the same buffer placement
     (serving_mix_batched_capacity: end to end from pinned host memory, or in
     HBM); the server's own closed-burst capacity is reported beside it.  Latency =
@@ -518,7 +520,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     from paper_2408_16551_amd.pfb import Server
     streams = workloads.serving_streams(seed)
     sv = Server(precision, max_streams=len(streams) + 4, max_active=max_active, hbm_budget_bytes=budget_bytes,
-                frames_per_step=frames_per_step, use_graph=True, max_channels=4096)
+                frames_per_step=frames_per_step, use_graph=use_graph, max_channels=4096)
     sids = [sv.stream(s.P, s.M, "c64") for s in streams]
     g = np.random.Generator(np.random.PCG64(seed + 7))
     max_len = 1 << 22

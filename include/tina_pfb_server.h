@@ -52,7 +52,12 @@ typedef struct tina_server_config {
     int32_t max_queued;        /* requests waiting for admission; submit returns BUSY beyond */
     int64_t hbm_budget_bytes;  /* device arena for request input and output buffers */
     int64_t frames_per_step;   /* frames of work per request per step with every slot busy, >= 1 */
-    int32_t use_graph;         /* nonzero: each step replays a captured HIP graph */
+    int32_t use_graph;         /* nonzero: each step replays a captured HIP graph (every
+                                  variant captured at creation); zero: plain launches (every
+                                  kernel variant launched once at creation).  A replay leaves
+                                  the device ~8 us longer idle between two steps; plain
+                                  launches cost more host time per step, which overlaps the
+                                  step in flight */
     int32_t max_channels;      /* largest P any stream will use (sizes the step workspace) */
 } tina_server_config;
 

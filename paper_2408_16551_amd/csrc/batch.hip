@@ -109,6 +109,7 @@ struct tina_pfb_batch_s {
     std::map<std::string, StepGraph> graphs;
     int64_t graph_gemm_grid = 0;  // GEMM grid the step graphs are captured with (0: no graphs)
     bool frame_stage = true;      // long per-frame scaled items run the single-pass frame stage
+    bool one_stream = false;      // every call comes on one stream: no order event is recorded
     StreamOrder order;            // every call shares ws, amax, fexp and d_table
 
     void release() {
@@ -442,7 +443,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
     // Launch errors are read with hipGetLastError: a status left by an earlier
     // query of a pending event (hipErrorNotReady) must not be read as one.
     (void)hipGetLastError();
-    HIP_TRY(b->order.begin(s));
+    if (!b->one_stream) HIP_TRY(b->order.begin(s));
     for (const GroupPlan& g : groups) {
         const int k = b->next_table;
         b->next_table ^= 1;
@@ -497,7 +498,7 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
             }
         }
     }
-    HIP_TRY(b->order.end(s));
+    if (!b->one_stream) HIP_TRY(b->order.end(s));
     return TINA_OK;
 }
 
@@ -530,10 +531,15 @@ void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
     b->graph_gemm_grid = g;
 }
 
-// Used by the server: steps keep every per-frame scaled item in the three FIR
+// Used by the server, which owns the batch and runs every step on its one
+// compute stream: steps keep every per-frame scaled item in the three FIR
 // launches (a step's items are short; a frame-stage unit's latency would set
-// the step's length).
-void batch_disable_frame_stage(tina_pfb_batch_s* b) { b->frame_stage = false; }
+// the step's length), and no event orders a call after the previous one (a
+// recorded event leaves the device idle for ~5 us between two steps).
+void batch_set_server_mode(tina_pfb_batch_s* b) {
+    b->frame_stage = false;
+    b->one_stream = true;
+}
 
 // Used by the server: run one step's items, through the cached step graph
 // when use_graph is set.  The server builds a step only after retiring the
@@ -543,13 +549,9 @@ tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hi
     tina_status st = validate(b, w, n, frames);
     if (st != TINA_OK) return st;
     DeviceScope ds(b->device);
-    Tune tune;  // graph steps keep the default launch shape: their graphs are captured in advance
-    if (!use_graph) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        auto it = g_tune_cache.find(signature(b, w, frames, n));
-        if (it != g_tune_cache.end()) tune = it->second;
-    }
+    // Steps keep the default launch shape: graph steps are captured in
+    // advance, and a step's mix of streams changes from one step to the next.
+    const Tune tune;
     return run_batch(b, w, n, s, tune, false, frames, use_graph, true);
 }
 
@@ -566,6 +568,24 @@ tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s) {
             for (int wide = 0; wide < n_wide; ++wide) {
                 tina_pfb_batch_s::StepGraph* sg = nullptr;
                 tina_status st = step_graph(b, s, tune, mt, exact != 0, wide != 0, sg);
+                if (st != TINA_OK) return st;
+            }
+    return TINA_OK;
+}
+
+// Used by a server that launches its steps without graphs: one launch of
+// every kernel variant a step can use, on an empty table (every stage's
+// unit ranges are empty, so each block returns at once), so that a first
+// step does not pay for loading them.
+tina_status batch_warm_kernels(tina_pfb_batch_s* b, hipStream_t s) {
+    DeviceScope ds(b->device);
+    const Tune tune;
+    HIP_TRY(hipMemsetAsync(b->d_table, 0, sizeof(BatchTable), s));
+    const int n_wide = form_fir_qmode(b->form) != 0 ? 2 : 1;
+    for (int mt = 1; mt <= 64; mt *= 2)
+        for (int exact = 1; exact >= (mt == 1 ? 1 : 0); --exact)
+            for (int wide = 0; wide < n_wide; ++wide) {
+                tina_status st = launch_stages(b, s, tune, mt, exact != 0, wide != 0, true, 8);
                 if (st != TINA_OK) return st;
             }
     return TINA_OK;

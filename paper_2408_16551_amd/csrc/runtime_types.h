@@ -150,6 +150,9 @@ struct tina_pfb_work;
 tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStream_t s, bool use_graph);
 // Bound on the GEMM tiles of one step (fixes the grid of captured steps).
 void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles);
-void batch_disable_frame_stage(tina_pfb_batch_s* b);
+// Launches every step kernel variant once on an empty table (no graphs).
+tina_status batch_warm_kernels(tina_pfb_batch_s* b, hipStream_t s);
+// A batch owned by a server: one stream, no frame stage.
+void batch_set_server_mode(tina_pfb_batch_s* b);
 // Captures every step-graph variant in advance (needs the bound above).
 tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s);

@@ -292,9 +292,9 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
     const int64_t ws = (int64_t)c->max_active * c->frames_per_step * 2 * c->max_channels * 4;
     tina_status st = tina_pfb_batch_create(c->device, c->precision, c->max_active, std::max<int64_t>(ws, 1 << 20), &sv->batch);
     if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
+    batch_set_server_mode(sv->batch);
     // Largest GEMM tile count of a step: every slot with frames_per_step
     // frames of the widest stream (128 x 128 tiles, N = 2 * max_channels).
-    batch_disable_frame_stage(sv->batch);
     batch_set_graph_bound(sv->batch, (int64_t)c->max_active * ((c->frames_per_step + kGemmBM - 1) / kGemmBM) *
                                          ((2 * (int64_t)c->max_channels + kGemmBN - 1) / kGemmBN));
     if (hipStreamCreateWithFlags(&sv->s_comp, hipStreamNonBlocking) != hipSuccess ||
@@ -306,11 +306,11 @@ tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) 
         if (hipEventCreate(&e) != hipSuccess) return bail(TINA_ERR_DEVICE, "server_create: events");
         sv->ev_pool.push_back(e);
     }
-    if (c->use_graph) {  // every step graph now, none while requests run
-        st = batch_prepare_graphs(sv->batch, sv->s_comp);
-        if (st == TINA_OK && hipStreamSynchronize(sv->s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
-        if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
-    }
+    // Every step graph now, none while requests run; without graphs, every
+    // kernel variant is launched once now.
+    st = c->use_graph ? batch_prepare_graphs(sv->batch, sv->s_comp) : batch_warm_kernels(sv->batch, sv->s_comp);
+    if (st == TINA_OK && hipStreamSynchronize(sv->s_comp) != hipSuccess) st = TINA_ERR_DEVICE;
+    if (st != TINA_OK) return bail(st, std::string("server_create: ") + tina_last_error());
     sv->th = std::thread([sv] { sv->loop(); });
     *out = sv;
     return TINA_OK;

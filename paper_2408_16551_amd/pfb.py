@@ -447,7 +447,7 @@ class Server:
     """Continuous-batching channelizer server (one thread, one device)."""
 
     def __init__(self, precision: str = "fp32", max_streams: int = 64, max_active: int = 32, max_queued: int = 4096,
-                 hbm_budget_bytes: int = 8 << 30, frames_per_step: int = 256, use_graph: bool = True,
+                 hbm_budget_bytes: int = 8 << 30, frames_per_step: int = 256, use_graph: bool = False,
                  max_channels: int = 4096, device: int = 0):
         c = _ServerConfig()
         c.struct_size = ctypes.sizeof(_ServerConfig)

@@ -78,7 +78,7 @@ def _one_shot(reqs, precision, streams=STREAMS):
     return ref
 
 
-@pytest.mark.parametrize("precision,use_graph", [("fp32", True), ("fp32", False), ("bf16x3", True), ("fp8", True)])
+@pytest.mark.parametrize("precision,use_graph", [("fp32", True), ("fp32", False), ("bf16x3", True), ("fp8", True), ("fp8", False)])
 def test_server_streams_equal_one_shot_bitwise(precision, use_graph):
     reqs = _workload(seed=1)
     got, results, stats = _serve(reqs, precision, use_graph)
