@@ -141,8 +141,10 @@ typedef struct tina_pfb_desc {
  *   TINA_DFT_FACTORED  a factored (four-step) DFT, P = P1 * P2: P2 DFTs of size
  *                      P1, twiddles, P1 DFTs of size P2, each size-P1/P2 DFT a
  *                      small matrix product on the MFMA units in FP32 -- 8 P (P1 + P2)
- *                      flops per frame instead of 8 P^2.  FP32 only; 256 <= P <= 4096;
- *                      single-stream execute only (not in batches or a server).
+ *                      flops per frame instead of 8 P^2.  FP32 only; 256 <= P <= 4096.
+ *                      Also in FP32 batches (one launch per channel count and
+ *                      input type over those items' frames) and in an FP32
+ *                      server created with this algorithm.
  *   TINA_DFT_FUSED     the dense product with the polyphase FIR fused into it:
  *                      each matrix-product tile forms its rows of FIR output
  *                      from the input stream in on-chip memory (a sliding

@@ -28,7 +28,10 @@ extern "C" {
 typedef struct tina_pfb_batch_s* tina_pfb_batch_t;
 
 /* One stream chunk of a batch.  plan: a TINA_OUT_PFB plan on the batch's
- * device with the batch's precision.  state: NULL (zero history, nothing
+ * device with the batch's precision, taking the dense DFT or (FP32) the
+ * factored one: the factored items' DFTs run as one launch per channel
+ * count and input type instead of the GEMM stage, and a batch may mix both
+ * (fused or compensated plans: UNSUPPORTED).  state: NULL (zero history, nothing
  * retained) or a state of that plan; a state may appear only once per batch.
  * d_in: n_samples samples (device, aligned to the sample size).  d_out: room
  * for out_capacity_frames output rows (device, 8-byte aligned), row layout as

@@ -59,6 +59,11 @@ typedef struct tina_server_config {
                                   launches cost more host time per step, which overlaps the
                                   step in flight */
     int32_t max_channels;      /* largest P any stream will use (sizes the step workspace) */
+    int32_t dft_algorithm;     /* tina_dft_algorithm of every stream: TINA_DFT_DENSE, or
+                                  TINA_DFT_FACTORED with precision FP32 (stream P then in
+                                  [256, 4096]; steps run as plain launches).  Configurations
+                                  whose struct_size ends before this field: DENSE */
+    int32_t reserved_;         /* must be 0 */
 } tina_server_config;
 
 /* Create a server and start its thread.  The server owns the arena

@@ -109,6 +109,17 @@ struct tina_pfb_batch_s {
     std::map<std::string, StepGraph> graphs;
     int64_t graph_gemm_grid = 0;  // GEMM grid the step graphs are captured with (0: no graphs)
     bool frame_stage = true;      // long per-frame scaled items run the single-pass frame stage
+    // Items whose plan takes the factored DFT (FP32): one launch per (P,
+    // input type) over their frames, with the items' FftItem rows stored in
+    // the table buffer after the items (fft_offset).
+    struct FftGroup {
+        int P;
+        bool cplx, q64_ok;
+        int first, count;  // rows [first, first + count) of the table's FftItem array
+        int64_t F;         // frames of the group's items
+        const float *mat1, *mat3, *tw;
+    };
+    std::vector<FftGroup> fft_groups;
     bool one_stream = false;      // every call comes on one stream: no order event is recorded
     StreamOrder order;            // every call shares ws, amax, fexp and d_table
 
@@ -135,6 +146,11 @@ struct tina_pfb_batch_s {
 namespace {
 
 size_t table_size(int n) { return sizeof(BatchTable) + sizeof(BatchItem) * (size_t)(n > 1 ? n - 1 : 0); }
+// Byte offset of the factored-DFT rows (FftItem) after n items, and the
+// bytes a table of n items with nf such rows uploads.
+size_t fft_offset(int n) { return (table_size(n) + 15) / 16 * 16; }
+size_t upload_size(int n, int nf) { return nf > 0 ? fft_offset(n) + sizeof(FftItem) * (size_t)nf : table_size(n); }
+FftItem* fft_rows(BatchTable* t, int n) { return reinterpret_cast<FftItem*>(reinterpret_cast<uint8_t*>(t) + fft_offset(n)); }
 
 // Cost-balanced split of a stage's units into 8 contiguous ranges: item i has
 // units[i] units of cost cost[i] each.
@@ -180,8 +196,8 @@ tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vect
         const tina_pfb_plan_s* p = it.plan;
         if (!p) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: item " + std::to_string(i) + " has no plan");
         if (p->device != b->device) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: plan on another device");
-        if (p->dft_algorithm != TINA_DFT_DENSE)
-            return fail(TINA_ERR_UNSUPPORTED, "batch: plans with the factored DFT run through tina_pfb_execute only");
+        if (p->dft_algorithm != TINA_DFT_DENSE && p->dft_algorithm != TINA_DFT_FACTORED)
+            return fail(TINA_ERR_UNSUPPORTED, "batch: plans with the fused or compensated DFT run through tina_pfb_execute only");
         if (p->output != TINA_OUT_PFB || p->precision != b->form)
             return fail(TINA_ERR_INVALID_ARGUMENT, "batch: every plan must be a filter-bank plan of the batch's precision");
         if (it.n_samples < 0) return fail(TINA_ERR_INVALID_ARGUMENT, "batch: negative sample count");
@@ -232,6 +248,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
     };
 
     std::vector<int64_t> fu(g.count), gu(g.count), su(g.count), ru(g.count);
+    std::vector<int> fft_items;  // items taking the factored DFT
     std::vector<double> fc(g.count), gc(g.count), sc(g.count, 1.0), rc(g.count, 1.0);
     int64_t ws_off = 0, amax_off = 0, f0 = 0, g0 = 0, s0 = 0, r0 = 0;
     for (int i = 0; i < g.count; ++i) {
@@ -315,7 +332,9 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
             ru[i] = 0;
         }
         r0 += ru[i];
-        gu[i] = F > 0 ? ((F + tile_m - 1) / tile_m) * ((p->N + tile_n - 1) / tile_n) : 0;
+        const bool factored = p->dft_algorithm == TINA_DFT_FACTORED;
+        gu[i] = (F > 0 && !factored) ? ((F + tile_m - 1) / tile_m) * ((p->N + tile_n - 1) / tile_n) : 0;
+        if (factored && F > 0) fft_items.push_back(i);
         gc[i] = (double)p->K;
         bi.fir_unit0 = f0;
         bi.gemm_unit0 = g0;
@@ -332,6 +351,42 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
             su[i] = 0;
         }
         s0 += su[i];
+    }
+    // Factored-DFT rows, grouped by (P, input type) in item order; a group's
+    // rows number its frames one item after the other.
+    b->fft_groups.clear();
+    std::stable_sort(fft_items.begin(), fft_items.end(), [&](int x, int y) {
+        const tina_pfb_plan_s *px = w[g.first + x].plan, *py = w[g.first + y].plan;
+        return px->P != py->P ? px->P < py->P : px->cf < py->cf;
+    });
+    FftItem* rows = fft_rows(t, g.count);
+    for (size_t k = 0; k < fft_items.size(); ++k) {
+        const int i = fft_items[k];
+        const tina_pfb_plan_s* p = w[g.first + i].plan;
+        const BatchItem& bi = t->items[i];
+        if (b->fft_groups.empty() || b->fft_groups.back().P != p->P || b->fft_groups.back().cplx != (p->cf == 2)) {
+            tina_pfb_batch_s::FftGroup fg;
+            fg.P = p->P;
+            fg.cplx = p->cf == 2;
+            fg.q64_ok = true;
+            fg.first = (int)k;
+            fg.count = 0;
+            fg.F = 0;
+            fg.mat1 = p->fft_mat1;
+            fg.mat3 = p->fft_mat3;
+            fg.tw = p->fft_tw;
+            b->fft_groups.push_back(fg);
+        }
+        tina_pfb_batch_s::FftGroup& fg = b->fft_groups.back();
+        FftItem& r = rows[k];
+        r.y = bi.fir.y;
+        r.out = bi.gemm.out;
+        r.ldy = bi.fir.ldy;
+        r.ldo = bi.gemm.ldo;
+        r.f0 = fg.F;
+        fg.q64_ok = fg.q64_ok && r.ldy % 4 == 0 && ((uintptr_t)r.y & 15) == 0;
+        fg.F += bi.gemm.F;
+        fg.count += 1;
     }
     t->gemm_bn = tile_n;
     t->gemm_wide = wide ? 1 : 0;
@@ -384,6 +439,10 @@ tina_status launch_stages(tina_pfb_batch_s* b, hipStream_t s, const Tune& tune, 
         HIP_TRY(launch_fir_batch(b->d_table, max_m, all_exact, qmode, grid_fir, s, b->frame_stage));
     if (always || b->h_table->gemm_units > 0)
         HIP_TRY(launch_gemm_batch(b->d_table, b->form, qmode != 0, tune.gemm_tile_n, (int)grid_gemm, s, wide));
+    if (!always)  // factored-DFT items: never in a captured step (the groups change from call to call)
+        for (const tina_pfb_batch_s::FftGroup& fg : b->fft_groups)
+            HIP_TRY(launch_fft_batch(fft_rows(b->d_table, b->h_table->n_items) + fg.first, fg.count, fg.F, fg.P,
+                                     fg.cplx, fg.q64_ok, fg.mat1, fg.mat3, fg.tw, b->cus, s));
     if (always || b->h_table->st_units > 0) HIP_TRY(launch_gather_batch(b->d_table, b->cus * 2, s));
     return TINA_OK;
 }
@@ -455,13 +514,15 @@ tina_status run_batch(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hipStrea
         int max_m = 1;
         bool all_exact = true, wide = false;
         fill_table(b, w, frames, g, tune, dry, max_m, all_exact, wide);
-        HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, table_size(g.count), hipMemcpyHostToDevice, s));
+        int n_fft = 0;
+        for (const tina_pfb_batch_s::FftGroup& fg : b->fft_groups) n_fft += fg.count;
+        HIP_TRY(hipMemcpyAsync(b->d_table, b->h_table, upload_size(g.count, n_fft), hipMemcpyHostToDevice, s));
         if (!tables_retired || groups.size() > 1) {
             HIP_TRY(hipEventRecord(b->table_free[k], s));
             b->table_pending[k] = true;
         }
         tina_pfb_batch_s::StepGraph* sg = nullptr;
-        if (use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid) {
+        if (use_graph && b->graph_gemm_grid > 0 && gemm_grid(b->h_table) <= b->graph_gemm_grid && b->fft_groups.empty()) {
             tina_status st = step_graph(b, s, tune, max_m, all_exact, wide, sg);
             if (st != TINA_OK) return st;
             if (sg->gemm_node) {  // this step's GEMM grid: blocks past the tiles' ranges would only return
@@ -624,7 +685,7 @@ tina_status tina_pfb_batch_create(int device, int precision, int max_items, int6
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         b->cus = ((prop.multiProcessorCount + 7) / 8) * 8;
     b->ws_floats = workspace_bytes / 4;
-    b->table_bytes = table_size(max_items);
+    b->table_bytes = upload_size(max_items, max_items);
     auto bail = [&](tina_status st, const char* m) {
         b->release();
         delete b;

@@ -79,11 +79,47 @@ struct FftShape {
 // Padded position of complex output k in the staging buffer.
 __device__ __forceinline__ int out_pos(int k) { return 2 * k + 2 * (k >> 5); }
 
-template <int P1, int P2, bool CPLX>
-__global__ __launch_bounds__(256) void fft_dft_kernel(const float* __restrict__ y, int64_t ldy, int64_t F,
-                                                      const float* __restrict__ mat1, const float* __restrict__ mat3,
-                                                      const float* __restrict__ tw, float* __restrict__ out,
-                                                      int64_t ldo) {
+// Where frame f of a launch lives.  OneChunk: the frames of one call (rows
+// of y and out).  ItemFrames: the frames of several batch items with the
+// same P, one after the other (item i owns launch frames [f0_i, f0_i + F_i));
+// each frame is found by a binary search over the items' first frames.  The
+// arithmetic per frame is the same for both, so a batched item's output is
+// bit for bit that of its own call.
+struct OneChunk {
+    const float* y;
+    int64_t ldy;
+    float* out;
+    int64_t ldo, F;
+    __device__ const float* yrow(int64_t f) const { return y + f * ldy; }
+    __device__ float* orow(int64_t f) const { return out + f * ldo; }
+};
+struct ItemFrames {
+    const FftItem* it;
+    int n;
+    int64_t F;
+    __device__ int find(int64_t f) const {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (it[mid].f0 <= f) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ const float* yrow(int64_t f) const {
+        const FftItem& x = it[find(f)];
+        return x.y + (f - x.f0) * x.ldy;
+    }
+    __device__ float* orow(int64_t f) const {
+        const FftItem& x = it[find(f)];
+        return x.out + (f - x.f0) * x.ldo;
+    }
+};
+
+template <int P1, int P2, bool CPLX, class FA>
+__global__ __launch_bounds__(256) void fft_dft_kernel(const FA fa, const float* __restrict__ mat1,
+                                                      const float* __restrict__ mat3, const float* __restrict__ tw) {
+    const int64_t F = fa.F;
     using S = FftShape<P1, P2, CPLX>;
     extern __shared__ float lds[];
     float* M1 = lds;                                   // [2 P1][S_M1] (K rows x M cols), step 1 (transposed A)
@@ -104,7 +140,7 @@ __global__ __launch_bounds__(256) void fft_dft_kernel(const float* __restrict__ 
     for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
         __syncthreads();  // matrices written / previous frame's staging read
         // Frame into buf as [Yr; Yi]: row p1 (re) and K1/2 + p1 (im), column p2.
-        const float* yf = y + f * ldy;
+        const float* yf = fa.yrow(f);
         if constexpr (CPLX) {
             for (int i = tid; i < S::P; i += 256) {
                 const float2 v = *reinterpret_cast<const float2*>(yf + 2 * i);
@@ -216,7 +252,7 @@ __global__ __launch_bounds__(256) void fft_dft_kernel(const float* __restrict__ 
             }
         }
         __syncthreads();
-        float* of = out + f * ldo;
+        float* of = fa.orow(f);
         constexpr int KOUT = CPLX ? S::P : S::P / 2 + 1;
         for (int k = tid; k < KOUT; k += 256) {
             float2 v = make_float2(buf[out_pos(k)], buf[out_pos(k) + 1]);
@@ -245,9 +281,9 @@ constexpr int kFq = 64;                     // Q
 constexpr int kFqS = 2 * kFq + 2;           // A' row stride (floats)
 constexpr int kFqLds = 4 * (2 * kFq * kFq + kFq * kFqS);
 
-__global__ __launch_bounds__(256) void fft_q64_kernel(const float* __restrict__ y, int64_t ldy, int64_t F,
-                                                      const float* __restrict__ tw, float* __restrict__ out,
-                                                      int64_t ldo) {
+template <class FA>
+__global__ __launch_bounds__(256) void fft_q64_kernel(const FA fa, const float* __restrict__ tw) {
+    const int64_t F = fa.F;
     constexpr int Q = kFq, P = Q * Q;
     typedef float f32x16 __attribute__((ext_vector_type(16)));
     extern __shared__ float lds[];
@@ -291,7 +327,7 @@ __global__ __launch_bounds__(256) void fft_q64_kernel(const float* __restrict__ 
     // Frame loads: 2 P floats = 512 float4, two per thread.
     float4 pre[8];
     auto load_frame = [&](int64_t f) {
-        const float4* src = reinterpret_cast<const float4*>(y + f * ldy);
+        const float4* src = reinterpret_cast<const float4*>(fa.yrow(f));
 #pragma unroll
         for (int i = 0; i < 8; ++i) pre[i] = src[tid + 256 * i];
     };
@@ -352,7 +388,7 @@ __global__ __launch_bounds__(256) void fft_q64_kernel(const float* __restrict__ 
             }
         // X[k1 + Q k2]: element v of row block rb is k1 = 32 rb + 8 (v / 4) +
         // 4 h + v % 4, the lane's column (part r / 16, k2 = 16 w + r % 16).
-        float* of = out + f * ldo + 2 * (Q * (16 * w + (r & 15))) + (r >> 4);
+        float* of = fa.orow(f) + 2 * (Q * (16 * w + (r & 15))) + (r >> 4);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -361,12 +397,12 @@ __global__ __launch_bounds__(256) void fft_q64_kernel(const float* __restrict__ 
     }
 }
 
-template <int P1, int P2, bool CPLX>
-hipError_t launch_fft_t(const FftArgs& a, hipStream_t s) {
+template <int P1, int P2, bool CPLX, class FA>
+hipError_t launch_fft_t(const FA& fa, const float* mat1, const float* mat3, const float* tw, int cus, hipStream_t s) {
     using S = FftShape<P1, P2, CPLX>;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)fft_dft_kernel<P1, P2, CPLX>,
+        hipError_t e = hipFuncSetAttribute((const void*)fft_dft_kernel<P1, P2, CPLX, FA>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS_BYTES);
         if (e != hipSuccess) return e;
         attr = true;
@@ -374,11 +410,47 @@ hipError_t launch_fft_t(const FftArgs& a, hipStream_t s) {
     int blocks_per_cu = (160 * 1024) / (S::LDS_BYTES + 1024);
     if (blocks_per_cu < 1) blocks_per_cu = 1;
     if (blocks_per_cu > 4) blocks_per_cu = 4;
-    int64_t grid = (int64_t)a.cus * blocks_per_cu;
-    if (grid > a.F) grid = a.F;
-    hipLaunchKernelGGL((fft_dft_kernel<P1, P2, CPLX>), dim3((unsigned)grid), dim3(256), S::LDS_BYTES, s, a.y, a.ldy,
-                       a.F, a.mat1, a.mat3, a.tw, a.out, a.ldo);
+    int64_t grid = (int64_t)cus * blocks_per_cu;
+    if (grid > fa.F) grid = fa.F;
+    hipLaunchKernelGGL((fft_dft_kernel<P1, P2, CPLX, FA>), dim3((unsigned)grid), dim3(256), S::LDS_BYTES, s, fa, mat1,
+                       mat3, tw);
     return hipGetLastError();
+}
+
+// Complex P = 4096 with 16-byte aligned rows: the register-resident kernel.
+template <class FA>
+hipError_t launch_q64(const FA& fa, const float* tw, int cus, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)fft_q64_kernel<FA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kFqLds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int64_t grid = 2 * (int64_t)cus;  // two blocks per CU (65.5 KiB of LDS each)
+    if (grid > fa.F) grid = fa.F;
+    hipLaunchKernelGGL((fft_q64_kernel<FA>), dim3((unsigned)grid), dim3(256), kFqLds, s, fa, tw);
+    return hipGetLastError();
+}
+
+template <class FA>
+hipError_t launch_fft_any(const FA& fa, int P, bool cplx, bool q64_ok, const float* mat1, const float* mat3,
+                          const float* tw, int cus, hipStream_t s) {
+    if (fa.F <= 0) return hipSuccess;
+    if (cplx && P == kFq * kFq && q64_ok) return launch_q64(fa, tw, cus, s);
+    switch (P) {
+        case 256: return cplx ? launch_fft_t<16, 16, true>(fa, mat1, mat3, tw, cus, s)
+                              : launch_fft_t<16, 16, false>(fa, mat1, mat3, tw, cus, s);
+        case 512: return cplx ? launch_fft_t<32, 16, true>(fa, mat1, mat3, tw, cus, s)
+                              : launch_fft_t<32, 16, false>(fa, mat1, mat3, tw, cus, s);
+        case 1024: return cplx ? launch_fft_t<32, 32, true>(fa, mat1, mat3, tw, cus, s)
+                               : launch_fft_t<32, 32, false>(fa, mat1, mat3, tw, cus, s);
+        case 2048: return cplx ? launch_fft_t<64, 32, true>(fa, mat1, mat3, tw, cus, s)
+                               : launch_fft_t<64, 32, false>(fa, mat1, mat3, tw, cus, s);
+        case 4096: return cplx ? launch_fft_t<64, 64, true>(fa, mat1, mat3, tw, cus, s)
+                               : launch_fft_t<64, 64, false>(fa, mat1, mat3, tw, cus, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -413,29 +485,15 @@ hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStre
 }
 
 hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s) {
-    if (a.F <= 0) return hipSuccess;
-    if (a.cplx && a.P == kFq * kFq && a.ldy % 4 == 0 && ((uintptr_t)a.y & 15) == 0) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void*)fft_q64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               kFqLds);
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
-        int64_t grid = 2 * (int64_t)a.cus;  // two blocks per CU (65.5 KiB of LDS each)
-        if (grid > a.F) grid = a.F;
-        hipLaunchKernelGGL(fft_q64_kernel, dim3((unsigned)grid), dim3(256), kFqLds, s, a.y, a.ldy, a.F, a.tw, a.out,
-                           a.ldo);
-        return hipGetLastError();
-    }
-    switch (a.P) {
-        case 256: return a.cplx ? launch_fft_t<16, 16, true>(a, s) : launch_fft_t<16, 16, false>(a, s);
-        case 512: return a.cplx ? launch_fft_t<32, 16, true>(a, s) : launch_fft_t<32, 16, false>(a, s);
-        case 1024: return a.cplx ? launch_fft_t<32, 32, true>(a, s) : launch_fft_t<32, 32, false>(a, s);
-        case 2048: return a.cplx ? launch_fft_t<64, 32, true>(a, s) : launch_fft_t<64, 32, false>(a, s);
-        case 4096: return a.cplx ? launch_fft_t<64, 64, true>(a, s) : launch_fft_t<64, 64, false>(a, s);
-        default: return hipErrorInvalidValue;
-    }
+    const OneChunk fa{a.y, a.ldy, a.out, a.ldo, a.F};
+    const bool q64_ok = a.ldy % 4 == 0 && ((uintptr_t)a.y & 15) == 0;
+    return launch_fft_any(fa, a.P, a.cplx != 0, q64_ok, a.mat1, a.mat3, a.tw, a.cus, s);
+}
+
+hipError_t launch_fft_batch(const FftItem* items, int n, int64_t F, int P, bool cplx, bool q64_ok, const float* mat1,
+                            const float* mat3, const float* tw, int cus, hipStream_t s) {
+    const ItemFrames fa{items, n, F};
+    return launch_fft_any(fa, P, cplx, q64_ok, mat1, mat3, tw, cus, s);
 }
 
 }  // namespace tina

@@ -131,6 +131,18 @@ bool fft_supported(int P);
 void fft_factors(int P, int& P1, int& P2);
 hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStream_t s);
 hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s);
+// One batch item's frames in a batched factored-DFT launch (device array,
+// sorted by f0): FIR output rows y, output rows out, and the item's first
+// frame among the launch's frames.
+struct FftItem {
+    const float* y;
+    float* out;
+    int64_t ldy, ldo, f0;
+};
+// Every frame of n items with the same P and input type (F frames in all);
+// q64_ok: every y row is 16-byte aligned with ldy a multiple of 4 floats.
+hipError_t launch_fft_batch(const FftItem* items, int n, int64_t F, int P, bool cplx, bool q64_ok, const float* mat1,
+                            const float* mat3, const float* tw, int cus, hipStream_t s);
 
 // --------------------------------------------------------------- batched path
 // One item of a batched launch: the FIR and GEMM arguments of one stream

@@ -14,6 +14,7 @@
 //              arena buffers are freed and waiters are woken.
 // Requests that arrive while a step runs are admitted before the next one.
 #include <stddef.h>
+#include <string.h>
 
 #include <algorithm>
 #include <chrono>
@@ -258,12 +259,22 @@ void tina_server_s::loop() {
 
 extern "C" {
 
-tina_status tina_server_create(const tina_server_config* c, tina_server_t* out) {
-    if (!c || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: NULL argument");
+tina_status tina_server_create(const tina_server_config* c_in, tina_server_t* out) {
+    if (!c_in || !out) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: NULL argument");
     *out = nullptr;
-    if (c->struct_size < sizeof(tina_server_config)) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: struct_size too small");
+    // Configurations that end before dft_algorithm take the dense DFT.
+    if (c_in->struct_size < offsetof(tina_server_config, dft_algorithm))
+        return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: struct_size too small");
+    tina_server_config cfg{};
+    memcpy(&cfg, c_in, std::min<size_t>(c_in->struct_size, sizeof(cfg)));
+    cfg.struct_size = sizeof(cfg);
+    const tina_server_config* c = &cfg;
     if (c->precision < TINA_PREC_FP32 || c->precision > TINA_PREC_MXFP8)
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: unknown precision");
+    if (c->dft_algorithm != TINA_DFT_DENSE && c->dft_algorithm != TINA_DFT_FACTORED)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: dft_algorithm must be DENSE or FACTORED");
+    if (c->dft_algorithm == TINA_DFT_FACTORED && c->precision != TINA_PREC_FP32)
+        return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: the factored DFT is FP32 only");
     if (c->max_streams < 1 || c->max_active < 1 || c->max_queued < 1 || c->frames_per_step < 1 ||
         c->hbm_budget_bytes < 4096)
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: max_streams, max_active, max_queued, frames_per_step "
@@ -368,6 +379,7 @@ tina_status tina_server_stream_create(tina_server_t sv, int32_t P, int32_t M, in
         d.output = TINA_OUT_PFB;
         d.device = sv->cfg.device;
         d.workspace_bytes = -1;  // used through the server's batch only
+        d.dft_algorithm = sv->cfg.dft_algorithm;
         tina_status st = tina_pfb_plan(&d, &plan);
         if (st != TINA_OK) return st;
         sv->plans[key] = plan;

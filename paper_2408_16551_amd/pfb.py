@@ -18,6 +18,7 @@ SAMPLE = {"r32": 0, "c64": 1}
 WINDOW = {"rect": 0, "hann": 1, "hamming": 2, "blackman": 3, "custom": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5, "mxfp8": 6}
 OUTPUT = {"pfb": 0, "fir": 1, "inverse": 2}
+DFT = {"dense": 0, "factored": 1, "fused": 2, "compensated": 3}
 
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
           5: "BUSY", 6: "NOT_READY", 7: "TOO_LARGE", 8: "TIMEOUT", 9: "CANCELLED"}
@@ -55,7 +56,8 @@ class _ServerConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_streams", ctypes.c_int32), ("max_active", ctypes.c_int32), ("max_queued", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("frames_per_step", ctypes.c_int64),
-                ("use_graph", ctypes.c_int32), ("max_channels", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("max_channels", ctypes.c_int32),
+                ("dft_algorithm", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -224,7 +226,7 @@ class Plan:
         d.sample_type, d.window = SAMPLE[sample_type], WINDOW[window]
         d.precision, d.output, d.device = PRECISION[precision], OUTPUT[output], int(device)
         d.workspace_bytes = int(workspace_bytes)
-        d.dft_algorithm = {"dense": 0, "factored": 1, "fused": 2, "compensated": 3}[dft]
+        d.dft_algorithm = DFT[dft]
         self._custom = None
         if custom_taps is not None:
             self._custom = np.ascontiguousarray(custom_taps, dtype=np.float64)
@@ -448,13 +450,14 @@ class Server:
 
     def __init__(self, precision: str = "fp32", max_streams: int = 64, max_active: int = 32, max_queued: int = 4096,
                  hbm_budget_bytes: int = 8 << 30, frames_per_step: int = 256, use_graph: bool = False,
-                 max_channels: int = 4096, device: int = 0):
+                 max_channels: int = 4096, device: int = 0, dft: str = "dense"):
         c = _ServerConfig()
         c.struct_size = ctypes.sizeof(_ServerConfig)
         c.device, c.precision = int(device), PRECISION[precision]
         c.max_streams, c.max_active, c.max_queued = int(max_streams), int(max_active), int(max_queued)
         c.hbm_budget_bytes, c.frames_per_step = int(hbm_budget_bytes), int(frames_per_step)
         c.use_graph, c.max_channels = int(bool(use_graph)), int(max_channels)
+        c.dft_algorithm = DFT[dft]
         h = ctypes.c_void_p()
         check(load().tina_server_create(ctypes.byref(c), ctypes.byref(h)))
         self.handle = h

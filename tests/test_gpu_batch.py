@@ -174,6 +174,96 @@ def test_batch_with_states_chunked_equals_one_shot(precision):
         assert np.array_equal(np.concatenate(got[i]), one.cpu().numpy())
 
 
+# FP32 batches with factored-DFT plans: every channel count the factored DFT
+# takes (256..4096), real and complex input (complex 4096 runs the
+# register-resident kernel), an empty chunk, a chunk shorter than P, and dense
+# FP32 items in the same batch.
+FACTORED_MIX = [(256, 16, True, 256 * 37 + 5, "factored"), (512, 11, False, 512 * 60 + 3, "factored"),
+                (1024, 16, True, 1024 * 9, "factored"), (2048, 8, False, 2048 * 12 + 100, "factored"),
+                (4096, 8, True, 4096 * 6 + 17, "factored"), (512, 16, True, 0, "factored"),
+                (1024, 9, False, 300, "factored"), (1024, 16, True, 1024 * 11 + 7, "dense"),
+                (256, 16, True, 256 * 20, "factored"), (4096, 4, False, 4096 * 5 + 9, "factored"),
+                (4096, 8, True, 4096 * 3, "factored")]
+
+
+def _factored_items(mix, seed):
+    from paper_2408_16551_amd.pfb import Plan
+    plans, xs = [], []
+    for i, (P, M, cplx, N, dft) in enumerate(mix):
+        plans.append(Plan(P, M, "c64" if cplx else "r32", "hann", "fp32", "pfb", dft=dft))
+        xs.append(_rand(N, cplx, seed + i))
+    return plans, xs
+
+
+@pytest.mark.parametrize("workspace_mib", [256, 2])
+def test_batch_factored_equals_single_execute_bitwise(workspace_mib):
+    # 2 MiB of workspace: the items run in several groups, each with its own
+    # factored launches.
+    from paper_2408_16551_amd.pfb import Batch
+    plans, xs = _factored_items(FACTORED_MIX, seed=40)
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [p.alloc_out(max(1, p.output_frames(x.size))) for p, x in zip(plans, xs)]
+    b = Batch("fp32", max_items=16, workspace_bytes=workspace_mib << 20)
+    fw = b.execute([(p, x, o) for p, x, o in zip(plans, xd, outs)])
+    torch.cuda.synchronize()
+    for p, x, o, f in zip(plans, xd, outs, fw):
+        single = p(x)
+        torch.cuda.synchronize()
+        assert f == single.shape[0]
+        assert torch.equal(o[:f], single)
+
+
+def test_batch_factored_matches_oracle(oracle):
+    from paper_2408_16551_amd.pfb import Batch
+    mix = [(512, 16, True, 512 * 40 + 9, "factored"), (4096, 8, True, 4096 * 10, "factored"),
+           (1024, 16, False, 1024 * 30 + 5, "factored")]
+    plans, xs = _factored_items(mix, seed=50)
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [p.alloc_out(max(1, p.output_frames(x.size))) for p, x in zip(plans, xs)]
+    fw = Batch("fp32", max_items=4).execute([(p, x, o) for p, x, o in zip(plans, xd, outs)])
+    torch.cuda.synchronize()
+    for (P, M, cplx, N, _), x, o, f in zip(mix, xs, outs, fw):
+        h = oracle.window(P, M, "hann")
+        n = (N // P) * P
+        ref = oracle.pfb(x[:n], P, M, h)
+        assert rel_l2(o[:f].cpu().numpy(), ref) < 1e-5
+
+
+def test_batch_factored_with_states_chunked_equals_one_shot():
+    from paper_2408_16551_amd.pfb import Batch, State
+    mix = [(256, 16, True, 256 * 40 + 77, "factored"), (4096, 8, True, 4096 * 30 + 3, "factored"),
+           (1024, 13, False, 1024 * 50 + 500, "factored"), (1024, 16, True, 1024 * 19 + 9, "dense")]
+    plans, xs = _factored_items(mix, seed=60)
+    b = Batch("fp32", max_items=8)
+    states = [State(p) for p in plans]
+    cuts = [0.0, 0.13, 0.5, 0.51, 1.0]
+    got = [[] for _ in mix]
+    for a, c in zip(cuts[:-1], cuts[1:]):
+        items = []
+        for i, (p, x) in enumerate(zip(plans, xs)):
+            lo, hi = int(a * x.size), int(c * x.size)
+            xdc = torch.from_numpy(np.ascontiguousarray(x[lo:hi])).cuda()
+            out = p.alloc_out(max(1, p.output_frames(hi - lo, states[i])))
+            items.append((p, xdc, out, states[i]))
+        fw = b.execute(items)
+        torch.cuda.synchronize()
+        for i, (it, f) in enumerate(zip(items, fw)):
+            got[i].append(it[2][:f].cpu().numpy())
+    for i, (p, x) in enumerate(zip(plans, xs)):
+        one = p(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(np.concatenate(got[i]), one.cpu().numpy())
+
+
+def test_batch_rejects_compensated_plans():
+    from paper_2408_16551_amd.pfb import Batch, Plan, TinaError
+    p = Plan(256, 8, "c64", "hann", "fp32", "pfb", dft="compensated")
+    x = torch.from_numpy(_rand(256 * 10, True, 1)).cuda()
+    o = p.alloc_out(10)
+    with pytest.raises(TinaError):
+        Batch("fp32", max_items=2).execute([(p, x, o)])
+
+
 def test_batch_tune_then_execute_bitwise():
     from paper_2408_16551_amd.pfb import Batch
     plans, xs, outs = _items(MIX[:5], "fp32", seed=11)

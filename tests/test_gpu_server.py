@@ -94,6 +94,49 @@ def test_server_streams_equal_one_shot_bitwise(precision, use_graph):
         assert r["t_submit_us"] <= r["t_admit_us"] <= r["t_done_us"]
 
 
+FACTORED_STREAMS = [(256, 16, True), (512, 11, True), (256, 16, False), (1024, 9, True), (4096, 8, True)]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_server_factored_streams_equal_one_shot_bitwise(use_graph):
+    # FP32 server with the factored DFT (steps run as plain launches even when
+    # graphs are asked for): each stream's concatenated outputs equal one
+    # factored pass over its concatenated input.
+    from paper_2408_16551_amd.pfb import Plan, Server
+    reqs = _workload(seed=5, n_req=20, streams=FACTORED_STREAMS)
+    sv = Server("fp32", max_streams=len(FACTORED_STREAMS), max_active=6, hbm_budget_bytes=1 << 30,
+                frames_per_step=32, use_graph=use_graph, max_channels=4096, dft="factored")
+    sids = [sv.stream(P, M, "c64" if c else "r32") for P, M, c in FACTORED_STREAMS]
+    res = [0] * len(FACTORED_STREAMS)
+    pending = []
+    for st, x in reqs:
+        P = FACTORED_STREAMS[st][0]
+        frames = (res[st] + x.size) // P
+        res[st] = (res[st] + x.size) % P
+        out = np.full((frames, sv.out_rows(sids[st])), np.nan, dtype=np.complex64)
+        pending.append((st, sv.submit(sids[st], x, out), out))
+    got = [[] for _ in FACTORED_STREAMS]
+    for st, rid, out in pending:
+        r = sv.wait(rid, timeout_s=60)
+        assert r["status"] == 0
+        got[st].append(out)
+    sv.close()
+    for st, (P, M, c) in enumerate(FACTORED_STREAMS):
+        xs = [x for t, x in reqs if t == st]
+        if not xs:
+            continue
+        plan = Plan(P, M, "c64" if c else "r32", "hann", "fp32", "pfb", dft="factored")
+        ref = plan(torch.from_numpy(np.concatenate(xs)).cuda()).cpu().numpy()
+        assert np.array_equal(np.concatenate(got[st]), ref)
+
+
+def test_server_factored_needs_fp32():
+    from paper_2408_16551_amd.pfb import Server, TinaError
+    with pytest.raises(TinaError):
+        Server("bf16x3", max_streams=1, max_active=1, hbm_budget_bytes=1 << 20, frames_per_step=16,
+               max_channels=256, dft="factored")
+
+
 def test_server_alone_equals_in_mix():
     reqs = _workload(seed=2)
     mixed, _, _ = _serve(reqs, "bf16x3")
