@@ -360,11 +360,12 @@ def sampled_check(oracle_obj, cases, seed, n_frames=64):
             "frames_per_stream": f"first M+1, last, {n_frames} random"}
 
 
-def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5, oracle_obj=None):
+def batched_bench(torch, precisions=("fp32", "bf16x3", "fp32/factored"), steps=5, oracle_obj=None):
     """The ragged batch: 64 complex64 streams, log-uniform lengths 2^18-2^22,
     channels from {256, 512, 1024}, 16 taps, one persistent launch per stage,
-    autotuned launch shapes.  With an oracle: 4 seeded items of the timed
-    batch are checked on sampled frames."""
+    autotuned launch shapes ("fp32/factored": FP32 with the factored DFT,
+    one launch per channel count in place of the GEMM stage).  With an
+    oracle: 4 seeded items of the timed batch are checked on sampled frames."""
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Batch, Plan
     specs, xs = workloads.ragged_batch()
@@ -372,8 +373,9 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5, oracle_obj=None
     xd = [torch.from_numpy(x).cuda() for x in xs]
     res = {"streams": len(specs), "samples": total,
            "channels_mix": {str(P): sum(1 for s in specs if s.P == P) for P in sorted({s.P for s in specs})}}
-    for prec in precisions:
-        plans = {P: Plan(P, 16, "c64", "hann", prec, workspace_bytes=-1) for P in {s.P for s in specs}}
+    for entry in precisions:
+        prec, dft = (entry.split("/") + ["dense"])[:2]
+        plans = {P: Plan(P, 16, "c64", "hann", prec, workspace_bytes=-1, dft=dft) for P in {s.P for s in specs}}
         outs = [torch.empty((x.size // s.P, s.P), dtype=torch.complex64, device="cuda") for s, x in zip(specs, xs)]
         items = [(plans[s.P], x, o) for s, x, o in zip(specs, xd, outs)]
         b = Batch(prec, max_items=len(items), workspace_bytes=2 << 30)
@@ -387,14 +389,14 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5, oracle_obj=None
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / steps
         flops = sum(dft_flops_per_frame(s.P, True) * (x.size // s.P) for s, x in zip(specs, xs))
-        res[prec] = {"gsps": round(total / sec / 1e9, 3), "ms_per_batch": round(sec * 1e3, 3),
-                     "dft_useful_tflops_incl_fir": round(flops / sec / 1e12, 2),
-                     "tuned": {"fir_frames_per_thread_mult": tf, "gemm_tile_n": tile_n}}
+        res[entry] = {"gsps": round(total / sec / 1e9, 3), "ms_per_batch": round(sec * 1e3, 3),
+                      "dft_useful_tflops_incl_fir": round(flops / sec / 1e12, 2),
+                      "tuned": {"fir_frames_per_thread_mult": tf, "gemm_tile_n": tile_n}}
         if oracle_obj is not None:
             pick = np.random.Generator(np.random.PCG64(77)).choice(len(items), size=4, replace=False)
-            res[prec]["check"] = sampled_check(
+            res[entry]["check"] = sampled_check(
                 oracle_obj, [(xs[i], specs[i].P, 16, outs[i].cpu().numpy()) for i in sorted(pick)], seed=78)
-        log(f"[bench] batched {prec}: {res[prec]}")
+        log(f"[bench] batched {entry}: {res[entry]}")
         b.close()
         del outs, items
     return res
@@ -403,15 +405,15 @@ def batched_bench(torch, precisions=("fp32", "bf16x3"), steps=5, oracle_obj=None
 _BATCHED_CAPACITY = {}
 
 
-def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5):
+def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5, dft="dense"):
     """Capacity C of the batched path on the serving mix: one request of
     log-uniform length 2^16-2^22 on each of the 64 logical streams, run as one
     tina_pfb_batch_execute (every item with its stream's plan and state),
     closed loop, inputs and outputs in HBM.  host=True: end to end from pinned
     host buffers (each pass copies every input in, runs the batch and copies
     every output back, in order on one stream).  GSamples/s."""
-    if (precision, host) in _BATCHED_CAPACITY:
-        return _BATCHED_CAPACITY[(precision, host)]
+    if (precision, host, dft) in _BATCHED_CAPACITY:
+        return _BATCHED_CAPACITY[(precision, host, dft)]
     from paper_2408_16551_amd import workloads
     from paper_2408_16551_amd.pfb import Batch, Plan, State
     streams = workloads.serving_streams(seed)
@@ -420,7 +422,7 @@ def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5
     plans = {}
     for s in streams:
         if (s.P, s.M) not in plans:
-            plans[(s.P, s.M)] = Plan(s.P, s.M, "c64", "hann", precision, workspace_bytes=-1)
+            plans[(s.P, s.M)] = Plan(s.P, s.M, "c64", "hann", precision, workspace_bytes=-1, dft=dft)
     src = torch.from_numpy(workloads.random_tone_stream(g, int(lens.max()), 4)).cuda()
     items, states = [], []
     for s, n in zip(streams, lens):
@@ -456,7 +458,7 @@ def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5
         st.close()
     for p in plans.values():
         p.close()
-    _BATCHED_CAPACITY[(precision, host)] = cap
+    _BATCHED_CAPACITY[(precision, host, dft)] = cap
     log(f"[bench] serving mix, batched path capacity {precision}{' from host buffers' if host else ''}: "
         f"{cap / 1e9:.2f} GS/s")
     return cap
@@ -500,7 +502,7 @@ def serving_check(torch, sv, pool, device, oracle_obj, seed, n_req=16):
 
 
 def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005, device=False,
-                  frames_per_step=1024, oracle_obj=None, max_active=64, use_graph=False):
+                  frames_per_step=1024, oracle_obj=None, max_active=64, use_graph=False, dft="dense"):
     """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
     1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
     random stream, length log-uniform 2^16-2^22.  The server runs up to
@@ -520,7 +522,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     from paper_2408_16551_amd.pfb import Server
     streams = workloads.serving_streams(seed)
     sv = Server(precision, max_streams=len(streams) + 4, max_active=max_active, hbm_budget_bytes=budget_bytes,
-                frames_per_step=frames_per_step, use_graph=use_graph, max_channels=4096)
+                frames_per_step=frames_per_step, use_graph=use_graph, max_channels=4096, dft=dft)
     sids = [sv.stream(s.P, s.M, "c64") for s in streams]
     g = np.random.Generator(np.random.PCG64(seed + 7))
     max_len = 1 << 22
@@ -566,7 +568,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
         sv.wait(rid)
         free_out.append(oi)
     cap_server = float(L.sum()) / (time.perf_counter() - t0)
-    cap = serving_mix_batched_capacity(torch, precision, host=not device)
+    cap = serving_mix_batched_capacity(torch, precision, host=not device, dft=dft)
     mean_len = float(np.mean(lens(100000)))
     lam = rho * cap / mean_len
     # open loop: every request is drawn before the clock starts (stream, input
@@ -661,7 +663,7 @@ def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0
     pa = np.array(parts[n_warm:], dtype=np.float64)
     breakdown = {name: {"p50": round(float(np.percentile(pa[:, j], 50)), 3), "p99": round(float(np.percentile(pa[:, j], 99)), 3)}
                  for j, name in enumerate(("submit_lag_ms", "admission_ms", "to_first_step_ms", "steps_ms", "steps"))}
-    return {"precision": precision, "hbm_budget_bytes": budget_bytes, "rho": rho,
+    return {"precision": precision if dft == "dense" else f"{precision}/{dft}", "hbm_budget_bytes": budget_bytes, "rho": rho,
             "buffers": "device (in place)" if device else "host (pinned; copied in and out)",
             "frames_per_step": frames_per_step, "max_active": max_active,
             "capacity_gsps_batched_path": round(cap / 1e9, 3), "capacity_includes_copies": not device,
@@ -810,8 +812,9 @@ def main():
         else:
             result["serving"] = [serving_bench(torch, prec, bud, oracle_obj=o) for prec in ("fp8", "bf16x3")
                                  for bud in (8 << 30, 256 << 20)]
-            result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho, oracle_obj=o)
-                                  for rho in (0.5, 0.8) for prec in ("fp8", "bf16x3")]
+            result["serving"] += [serving_bench(torch, prec, 8 << 30, device=True, rho=rho, oracle_obj=o, dft=dft)
+                                  for rho in (0.5, 0.8) for prec, dft in (("fp8", "dense"), ("bf16x3", "dense"),
+                                                                          ("fp32", "factored"))]
 
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
