@@ -259,6 +259,41 @@ def cpu_context(w, target_s=4.0):
     return res
 
 
+def cpu_context_precision(wd, frames=512, numpy_frames=4096, reps=3):
+    """The CPU on the precision workload (complex input, 4096 channels,
+    8 taps): the FP64 oracle on every host core over its first `frames`
+    frames, and the NumPy filter bank in FP32 and FP64 over its first
+    `numpy_frames` frames; each the median of `reps` runs."""
+    from oracle import Oracle
+    o = Oracle()
+    h = o.window(wd.P, wd.M, wd.window)
+    F = wd.x.size // wd.P
+    n = min(F, frames)
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        ref = o.pfb(wd.x, wd.P, wd.M, h, frames=np.arange(n, dtype=np.int64))
+        times.append(time.perf_counter() - t)
+    dt = sorted(times)[len(times) // 2]
+    res = {"workload": wd.name, "oracle": {"value": round(n * wd.P / dt / 1e9, 6), "unit": "GSamples/s",
+                                            "cores": o.threads(), "sample": f"first {n} of {F} frames, median of "
+                                                                          f"{reps}: {dt:.2f} s"}}
+    nf = min(F, numpy_frames)
+    xs = wd.x[: nf * wd.P]
+    for name, dt_ in (("fp32", np.complex64), ("fp64", np.complex128)):
+        numpy_pfb(xs[: 64 * wd.P], wd.P, wd.M, h, np.dtype(dt_))
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            X = numpy_pfb(xs, wd.P, wd.M, h, np.dtype(dt_))
+            times.append(time.perf_counter() - t)
+        sec = sorted(times)[len(times) // 2]
+        res[f"numpy_{name}"] = {"value": round(nf * wd.P / sec / 1e9, 6), "unit": "GSamples/s", "cores": 1,
+                                "rel_l2_vs_oracle": float(f"{rel_l2(X[:n], ref):.2e}"),
+                                "sample": f"first {nf} of {F} frames, median of {reps}: {sec:.2f} s"}
+    return res
+
+
 def ops_bench(torch, steps=10):
     """The standalone building blocks: unfold (GB/s of output written, the
     bound) and the direct FIR with arbitrary taps (GSamples/s)."""
@@ -820,6 +855,9 @@ def main():
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w)
         result["cpu_context"] = cpu_context(w)
+        wd = workloads.wide_dynamic_range()
+        result["cpu_context"]["precision_workload"] = cpu_context_precision(wd)
+        del wd
     print(json.dumps(result), flush=True)
 
 
