@@ -734,7 +734,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--serving-quick", action="store_true",
                     help="serving: only FP8 per-frame, device buffers, rho 0.5, 50 + 300 requests (for kernel traces)")
-    ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored,fp32/compensated",
+    ap.add_argument("--forms", default="fp32,bf16,bf16x3,fp16,fp16x3,fp8,mxfp8,fp32/factored,fp32/compensated,fp32/table",
                     help="comma-separated precision forms of the form tables (form or form/factored)")
     ap.add_argument("--form-workloads", default="real,wide",
                     help="comma-separated workloads of the form tables: real (1024-channel real stream), "

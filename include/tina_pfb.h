@@ -162,12 +162,21 @@ typedef struct tina_pfb_desc {
  *                      then scales with the partial sums of one tile instead
  *                      of the whole row, which keeps channels far below the
  *                      frame's strongest one accurate (Eq. (12) at a wide
- *                      dynamic range).  FP32 only; single-stream execute. */
+ *                      dynamic range).  FP32 only; single-stream execute.
+ *   TINA_DFT_TABLE     the dense FP32 product with the operand F of Eq. (12)
+ *                      never materialised: each matrix-product tile assembles
+ *                      its operand rows in on-chip memory from a P-entry
+ *                      twiddle table (cos, sin of 2 pi r / P, r = p k mod P),
+ *                      8 P bytes instead of the N x K operand (256 MiB at
+ *                      P = 4096 complex).  Same entries, so results are bit
+ *                      for bit those of TINA_DFT_DENSE.  FP32 only;
+ *                      single-stream execute. */
 typedef enum tina_dft_algorithm {
     TINA_DFT_DENSE = 0,
     TINA_DFT_FACTORED = 1,
     TINA_DFT_FUSED = 2,
-    TINA_DFT_COMPENSATED = 3
+    TINA_DFT_COMPENSATED = 3,
+    TINA_DFT_TABLE = 4
 } tina_dft_algorithm;
 
 typedef struct tina_pfb_plan_s* tina_pfb_plan_t;

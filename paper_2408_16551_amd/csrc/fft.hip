@@ -484,6 +484,11 @@ hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStre
     return hipGetLastError();
 }
 
+hipError_t launch_twiddle_table(float* tw, int P, hipStream_t s) {
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3((P + 255) / 256), dim3(256), 0, s, tw, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s) {
     const OneChunk fa{a.y, a.ldy, a.out, a.ldo, a.F};
     const bool q64_ok = a.ldy % 4 == 0 && ((uintptr_t)a.y & 15) == 0;

@@ -241,8 +241,25 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int
 // products) plus one rounding per tile, instead of a rounding at the size of
 // the whole running sum for each of the K products: channels far below the
 // frame's strongest one keep their accuracy.
-template <int FORM, int WN, bool COMP = false>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM, WN>& sm) {
+// The DFT operand's entry Bt[n][k] from the twiddle table tw (cos, sin of
+// 2 pi r / P for r < P, FP32-rounded from FP64 as the materialised operand
+// is), so both give the same bits.  Complex input: n = 2 channel + (im
+// output), k = 2 sample + (im input); real input: row 0 is X_0, row 1 X_{P/2}
+// (packed), row n >= 2 cos (even) or -sin (odd) of channel n / 2.
+__device__ __forceinline__ float table_entry(const float2* tw, int P, bool cplx, int n, int k) {
+    if (cplx) {
+        const float2 t = tw[((k >> 1) * (n >> 1)) & (P - 1)];
+        const int col_im = n & 1, row_im = k & 1;
+        return col_im == row_im ? t.x : (row_im ? t.y : -t.y);
+    }
+    if (n < 2) return (n == 1 && (k & 1)) ? -1.0f : 1.0f;
+    const float2 t = tw[(k * (n >> 1)) & (P - 1)];
+    return (n & 1) ? -t.y : t.x;
+}
+
+template <int FORM, int WN, bool COMP = false, bool TABLE = false>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0, GemmSmem<FORM, WN>& sm,
+                                          const float2* tws = nullptr) {
     constexpr int BN = 64 * WN, WC = 32 * WN;  // block tile columns, columns per wave
     using ft = FT<FORM>;
     static_assert(FORM == FORM_FP32 || FORM == FORM_BF16 || FORM == FORM_BF16X3, "FP32 A, converted to bf16 at most");
@@ -286,8 +303,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
                 const int64_t n = n0 + row;
                 const int64_t kb = (int64_t)k0 * EB + kc * 16;
-                if (n < g.N && kb < KB) rb[p][i] = *reinterpret_cast<const uint4*>(Bp[p] + n * KB + kb);
-                else rb[p][i] = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (TABLE) {  // FP32: 4 entries of row n from the LDS table
+                    static_assert(FORM == FORM_FP32, "the table form is FP32");
+                    const bool cplx = !g.real_pack;
+                    const int P = cplx ? g.K / 2 : g.K;
+                    float v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = k0 + kc * 4 + j;
+                        v[j] = (n < g.N && k < g.K) ? table_entry(tws, P, cplx, (int)n, k) : 0.0f;
+                    }
+                    rb[p][i] = __builtin_bit_cast(uint4, make_float4(v[0], v[1], v[2], v[3]));
+                } else {
+                    if (n < g.N && kb < KB) rb[p][i] = *reinterpret_cast<const uint4*>(Bp[p] + n * KB + kb);
+                    else rb[p][i] = make_uint4(0u, 0u, 0u, 0u);
+                }
             }
     };
 
@@ -1128,6 +1158,23 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
     gemm_tile<FORM, WN>(g, m0, n0, sm);
 }
 
+// FP32 with the DFT operand assembled from a P-entry twiddle table in LDS
+// (the table after the tile buffers, 8 P bytes, loaded once per block)
+// instead of read from the materialised N x K operand.
+template <int WN>
+__global__ __launch_bounds__(NT) void dft_gemm_table_kernel(GemmArgs g, int P) {
+    constexpr int BN = 64 * WN;
+    extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
+    GemmSmem<FORM_FP32, WN>& sm = *reinterpret_cast<GemmSmem<FORM_FP32, WN>*>(dyn);
+    float2* tws = reinterpret_cast<float2*>(dyn + sizeof(GemmSmem<FORM_FP32, WN>));
+    const float2* tw = reinterpret_cast<const float2*>(g.tw);
+    for (int r = threadIdx.x; r < P; r += NT) tws[r] = tw[r];  // gemm_tile's first barrier publishes it
+    const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+    int64_t m0, n0;
+    grouped_tile(xcd_logical_block(blockIdx.x, (int64_t)gridDim.x), nm, nn, BN, m0, n0);
+    gemm_tile<FORM_FP32, WN, false, true>(g, m0, n0, sm, tws);
+}
+
 // FP32 with compensated K accumulation: 128 x 128 tiles (the running sums
 // and the block accumulators of 2 x 2 MFMA blocks per wave fit 2 waves per
 // SIMD, so one wave's additions overlap the other's products).
@@ -1342,6 +1389,23 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
             case FORM_FP16X3: return (g.fexp && g.Aq1) ? launch_raw<FORM_FP16X3>(g, s) : hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
+    }
+    if (g.tw) {  // FP32, operand from the twiddle table
+        if (g.form != FORM_FP32 || g.compensated) return hipErrorInvalidValue;
+        constexpr int WN = 4, BN = 64 * WN;
+        const int P = g.real_pack ? g.K : g.K / 2;
+        const size_t lds = sizeof(GemmSmem<FORM_FP32, WN>) + 8 * (size_t)P;
+        static bool attr = false;
+        if (!attr) {  // up to P = 8192 (64 KiB of table)
+            hipError_t e = hipFuncSetAttribute((const void*)dft_gemm_table_kernel<WN>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(sizeof(GemmSmem<FORM_FP32, WN>) + 8 * 8192));
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
+        hipLaunchKernelGGL((dft_gemm_table_kernel<WN>), dim3((unsigned)(nm * nn)), dim3(NT), lds, s, g, P);
+        return hipGetLastError();
     }
     if (g.compensated) {
         if (g.form != FORM_FP32) return hipErrorInvalidValue;

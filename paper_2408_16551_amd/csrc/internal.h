@@ -104,6 +104,7 @@ struct GemmArgs {
     const uint8_t* Aqs;
     const int32_t* fexp;   // per-frame scaled forms with A in operand form: A row f carries 2^-fexp[f]
     int32_t compensated;   // FP32 only: compensated K accumulation (TwoSum per K tile)
+    const float* tw;       // FP32 only, non-null: Bt assembled from this P x (cos, sin) twiddle table (B0 unused)
 };
 hipError_t launch_dft_gemm(const GemmArgs& a, hipStream_t s);
 // The FIR fused into the FP32 GEMM (g.A unused; x describes the input stream
@@ -130,6 +131,8 @@ struct FftArgs {
 bool fft_supported(int P);
 void fft_factors(int P, int& P1, int& P2);
 hipError_t launch_fft_tables(float* mat1, float* mat3, float* tw, int P, hipStream_t s);
+// tw (P x 2): cos, sin of 2 pi r / P in FP64, rounded to FP32.
+hipError_t launch_twiddle_table(float* tw, int P, hipStream_t s);
 hipError_t launch_fft_dft(const FftArgs& a, hipStream_t s);
 // One batch item's frames in a batched factored-DFT launch (device array,
 // sorted by f0): FIR output rows y, output rows out, and the item's first

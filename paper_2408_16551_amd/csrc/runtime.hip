@@ -45,7 +45,7 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
     const int64_t ws_req = d->struct_size >= offsetof(tina_pfb_desc, dft_algorithm) ? d->workspace_bytes : 0;
     const int dft_alg = d->struct_size >= offsetof(tina_pfb_desc, reserved_) ? d->dft_algorithm : TINA_DFT_DENSE;
     if (dft_alg != TINA_DFT_DENSE && dft_alg != TINA_DFT_FACTORED && dft_alg != TINA_DFT_FUSED &&
-        dft_alg != TINA_DFT_COMPENSATED)
+        dft_alg != TINA_DFT_COMPENSATED && dft_alg != TINA_DFT_TABLE)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown dft_algorithm");
     if (d->sample_type != TINA_SAMPLE_R32 && d->sample_type != TINA_SAMPLE_C64)
         return fail(TINA_ERR_INVALID_ARGUMENT, "plan: unknown sample_type");
@@ -76,6 +76,8 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
         return fail(TINA_ERR_UNSUPPORTED, "plan: the factored DFT needs FP32 and 256 <= channels <= 4096");
     if (dft_alg == TINA_DFT_COMPENSATED && d->output == TINA_OUT_PFB && d->precision != TINA_PREC_FP32)
         return fail(TINA_ERR_UNSUPPORTED, "plan: compensated accumulation needs FP32");
+    if (dft_alg == TINA_DFT_TABLE && d->output == TINA_OUT_PFB && d->precision != TINA_PREC_FP32)
+        return fail(TINA_ERR_UNSUPPORTED, "plan: the twiddle-table operand needs FP32");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TINA_ERR_DEVICE, "plan: no HIP device");
     if (d->device < 0 || d->device >= ndev) return fail(TINA_ERR_INVALID_ARGUMENT, "plan: bad device ordinal");
@@ -141,6 +143,10 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
                 hipMalloc(&p->fft_tw, sizeof(float) * 2 * p->P) != hipSuccess)
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: factored DFT tables");
             e = launch_fft_tables(p->fft_mat1, p->fft_mat3, p->fft_tw, p->P, nullptr);
+        } else if (p->dft_algorithm == TINA_DFT_TABLE) {  // no N x K operand: P twiddles
+            if (hipMalloc(&p->fft_tw, sizeof(float) * 2 * p->P) != hipSuccess)
+                return bail(TINA_ERR_OUT_OF_MEMORY, "plan: twiddle table");
+            e = launch_twiddle_table(p->fft_tw, p->P, nullptr);
         } else if (form_mx(form)) {
             if (hipMalloc(&p->B[0], mx_codes_bytes(p->N, p->K)) != hipSuccess ||
                 hipMalloc(&p->B[1], (int64_t)p->N * (p->K / 32)) != hipSuccess)
@@ -354,6 +360,7 @@ tina_status execute_with(tina_pfb_plan_s* p, const void* d_in, int64_t n, void* 
             ga.Aqs = fa.qs;
             ga.fexp = fa.fexp;
             ga.compensated = p->dft_algorithm == TINA_DFT_COMPENSATED;
+            ga.tw = p->dft_algorithm == TINA_DFT_TABLE ? p->fft_tw : nullptr;
             HIP_TRY(timed(p->ev_dft, [&] { return launch_dft_gemm(ga, s); }));
         }
     }

@@ -18,7 +18,7 @@ SAMPLE = {"r32": 0, "c64": 1}
 WINDOW = {"rect": 0, "hann": 1, "hamming": 2, "blackman": 3, "custom": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "fp8": 5, "mxfp8": 6}
 OUTPUT = {"pfb": 0, "fir": 1, "inverse": 2}
-DFT = {"dense": 0, "factored": 1, "fused": 2, "compensated": 3}
+DFT = {"dense": 0, "factored": 1, "fused": 2, "compensated": 3, "table": 4}
 
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
           5: "BUSY", 6: "NOT_READY", 7: "TOO_LARGE", 8: "TIMEOUT", 9: "CANCELLED"}

@@ -305,7 +305,7 @@ def test_full_size_real_stream_sampled(oracle, real_stream_wl, precision):
 # accumulation over K of a row whose partial sums carry the strong tone.
 # Bounds: the measured worst channel rounded up by half.  Compensated
 # accumulation (error-free two-sum per K tile) brings FP32 under 1e-2.
-WORST_CHANNEL_BOUNDS = {"fp32": 0.16, "fp32/factored": 0.11, "fp32/compensated": 1e-2, "bf16": 180.0,
+WORST_CHANNEL_BOUNDS = {"fp32": 0.16, "fp32/factored": 0.11, "fp32/compensated": 1e-2, "fp32/table": 0.16, "bf16": 180.0,
                         "bf16x3": 0.37, "fp16": 28.0, "fp16x3": 0.06, "fp8": 5800.0, "mxfp8": 5800.0}
 
 
@@ -414,6 +414,42 @@ def test_compensated_streaming_bitwise_and_rejects_reduced_forms():
     assert np.array_equal(got, one)
     with pytest.raises(TinaError) as e:
         Plan(P, M, "c64", "hann", "bf16x3", dft="compensated")
+    assert e.value.status == 2
+
+
+# ------------------------------------------ operand assembled from a twiddle table
+# The table holds the operand's own FP32 entries (cos, sin of 2 pi r / P), so
+# the product is bit for bit the dense one; covered: real and complex input,
+# P from 16 to 8192 (one block per CU when the table takes 32 KiB or more),
+# ragged frame counts and partial tiles.
+@pytest.mark.parametrize("P,M,cplx,frames", [(16, 4, False, 700), (64, 4, True, 300), (256, 8, True, 130),
+                                              (1024, 16, False, 200), (1024, 16, True, 61), (4096, 8, True, 40),
+                                              (8192, 2, False, 9), (2048, 5, True, 33)])
+def test_table_operand_equals_dense_bitwise_and_matches_oracle(oracle, P, M, cplx, frames):
+    from paper_2408_16551_amd.pfb import Plan
+    N = P * frames + P // 3
+    x = _rand(N, cplx, seed=31 * P + M)
+    print(f"table operand P={P} M={M} cplx={cplx} frames={frames}", flush=True)
+    dense = _run(Plan(P, M, "c64" if cplx else "r32", "hann", "fp32"), x)
+    X = _run(Plan(P, M, "c64" if cplx else "r32", "hann", "fp32", dft="table"), x)
+    assert np.array_equal(X, dense)
+    ref = oracle.pfb(x[: (N // P) * P], P, M, oracle.window(P, M, "hann"))
+    assert rel_l2(X, ref) < FP32_BOUND
+
+
+def test_table_operand_streaming_bitwise_and_rejects_reduced_forms():
+    from paper_2408_16551_amd.pfb import Plan, State, TinaError
+    P, M = 512, 12
+    N = P * 300 + 77
+    x = _rand(N, True, seed=10)
+    plan = Plan(P, M, "c64", "hann", "fp32", dft="table")
+    one = _run(plan, x)
+    st = State(plan)
+    cuts = [0, 500, P * 7, P * 150 + 3, N]
+    got = np.concatenate([_run(plan, np.ascontiguousarray(x[a:b]), state=st) for a, b in zip(cuts[:-1], cuts[1:])])
+    assert np.array_equal(got, one)
+    with pytest.raises(TinaError) as e:
+        Plan(P, M, "c64", "hann", "bf16", dft="table")
     assert e.value.status == 2
 
 
