@@ -273,6 +273,7 @@ tina_status tina_server_create(const tina_server_config* c_in, tina_server_t* ou
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: unknown precision");
     if (c->dft_algorithm != TINA_DFT_DENSE && c->dft_algorithm != TINA_DFT_FACTORED)
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: dft_algorithm must be DENSE or FACTORED");
+    if (c->reserved_ != 0) return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: reserved_ must be 0");
     if (c->dft_algorithm == TINA_DFT_FACTORED && c->precision != TINA_PREC_FP32)
         return fail(TINA_ERR_INVALID_ARGUMENT, "server_create: the factored DFT is FP32 only");
     if (c->max_streams < 1 || c->max_active < 1 || c->max_queued < 1 || c->frames_per_step < 1 ||

@@ -131,6 +131,15 @@ def test_server_config_validated_before_device(lib):
     assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
     c.frames_per_step, c.precision = 64, 17
     assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    c.precision, c.dft_algorithm = 2, 1           # factored DFT on a BF16x3 server
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    c.precision, c.dft_algorithm = 0, 3           # compensated: not a server algorithm
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    c.dft_algorithm, c.reserved_ = 1, 5
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    c.reserved_ = 0
+    c.struct_size = 16                            # ends before the fields it needs
+    assert lib.tina_server_create(ctypes.byref(c), ctypes.byref(h)) == 1
     assert not h.value
     r = pfb._Request()
     rid = ctypes.c_uint64()
