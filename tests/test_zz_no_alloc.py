@@ -27,13 +27,15 @@ def _bits(t):
     return torch.view_as_real(t).numpy() if t.is_complex() else t.numpy()
 
 
-CASES = [  # (P, M, sample type, precision, output, samples of the first call)
+CASES = [  # (P, M, sample type, precision (/DFT algorithm), output, samples of the first call)
     (1024, 16, "r32", "fp32", "pfb", 1024 * 3000 + 517),
     (1024, 12, "r32", "fp8", "pfb", 1024 * 2500 + 3),
     (512, 16, "c64", "bf16x3", "pfb", 512 * 2049 + 100),
     (256, 8, "c64", "fp16x3", "pfb", 256 * 3000 + 9),
     (1024, 16, "r32", "mxfp8", "pfb", 1024 * 1500),
     (4096, 8, "c64", "fp32", "fir", 4096 * 700 + 5),
+    (4096, 8, "c64", "fp32/factored", "pfb", 4096 * 600 + 7),
+    (1024, 16, "r32", "fp32/table", "pfb", 1024 * 900 + 33),
 ]
 
 
@@ -42,7 +44,8 @@ def test_noalloc_equals_execute_two_calls(P, M, st, prec, out, n1):
     from paper_2408_16551_amd.pfb import Plan
     print(f"noalloc: P={P} M={M} {st} {prec} {out} n1={n1}", flush=True)
     cplx = st == "c64"
-    plan = Plan(P, M, st, "hann", prec, out)
+    form, dft = (prec.split("/") + ["dense"])[:2]
+    plan = Plan(P, M, st, "hann", form, out, dft=dft)
     for n, seed in ((n1, 1), (n1 // 3 + 11, 2)):  # the second call is smaller
         x = torch.from_numpy(_x(n, seed, cplx)).cuda()
         ref = plan(x).clone()
