@@ -241,20 +241,30 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m0, int
 // products) plus one rounding per tile, instead of a rounding at the size of
 // the whole running sum for each of the K products: channels far below the
 // frame's strongest one keep their accuracy.
-// The DFT operand's entry Bt[n][k] from the twiddle table tw (cos, sin of
-// 2 pi r / P for r < P, FP32-rounded from FP64 as the materialised operand
-// is), so both give the same bits.  Complex input: n = 2 channel + (im
-// output), k = 2 sample + (im input); real input: row 0 is X_0, row 1 X_{P/2}
-// (packed), row n >= 2 cos (even) or -sin (odd) of channel n / 2.
-__device__ __forceinline__ float table_entry(const float2* tw, int P, bool cplx, int n, int k) {
-    if (cplx) {
-        const float2 t = tw[((k >> 1) * (n >> 1)) & (P - 1)];
-        const int col_im = n & 1, row_im = k & 1;
-        return col_im == row_im ? t.x : (row_im ? t.y : -t.y);
-    }
+// Operand entries from the twiddle table tw (cos, sin of 2 pi r / P for
+// r < P, FP32-rounded from FP64 as the materialised operand is), so both give
+// the same bits.  Real input: row 0 is X_0, row 1 X_{P/2} (packed), row
+// n >= 2 cos (even n) or -sin (odd n) of channel n / 2 at sample k.
+__device__ __forceinline__ float table_entry_real(const float2* tw, int P, int n, int k) {
     if (n < 2) return (n == 1 && (k & 1)) ? -1.0f : 1.0f;
     const float2 t = tw[(k * (n >> 1)) & (P - 1)];
     return (n & 1) ? -t.y : t.x;
+}
+
+// Four entries Bt[n][k..k+3] (k a multiple of 4; K, a multiple of 4, bounds
+// them all at once).  Complex input (n = 2 channel + im output, k = 2 sample
+// + im input) reads the table twice, for samples k/2 and k/2 + 1 of channel
+// n/2: (cos, sin) for the real output row, (-sin, cos) for the imaginary one.
+// Real input reads it four times.
+__device__ __forceinline__ float4 table_frag(const float2* tw, int P, bool cplx, int n, int k, int N, int K) {
+    if (n >= N || k >= K) return make_float4(0.f, 0.f, 0.f, 0.f);
+    if (cplx) {
+        const int ch = n >> 1, p0 = k >> 1;
+        const float2 t0 = tw[(p0 * ch) & (P - 1)], t1 = tw[((p0 + 1) * ch) & (P - 1)];
+        return (n & 1) ? make_float4(-t0.y, t0.x, -t1.y, t1.x) : make_float4(t0.x, t0.y, t1.x, t1.y);
+    }
+    return make_float4(table_entry_real(tw, P, n, k), table_entry_real(tw, P, n, k + 1),
+                       table_entry_real(tw, P, n, k + 2), table_entry_real(tw, P, n, k + 3));
 }
 
 template <int FORM, int WN, bool COMP = false, bool TABLE = false>
@@ -274,7 +284,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     constexpr int RD = SLAB / 32;                 // 16-byte reads per lane per slab
 
     uint8_t* As = sm.tiles;                 // NP pieces of BM x RS
-    uint8_t* Bs = sm.tiles + NP * BM * RS;  // NP pieces of BN x RS
+    uint8_t* Bs = sm.tiles + NP * BM * RS;  // NP pieces of BN x RS (not used by the table form)
+    const bool tcplx = !g.real_pack;        // table form: complex input, and P
+    const int tP = tcplx ? g.K / 2 : g.K;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -303,18 +315,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
                 const int64_t n = n0 + row;
                 const int64_t kb = (int64_t)k0 * EB + kc * 16;
-                if constexpr (TABLE) {  // FP32: 4 entries of row n from the LDS table
-                    static_assert(FORM == FORM_FP32, "the table form is FP32");
-                    const bool cplx = !g.real_pack;
-                    const int P = cplx ? g.K / 2 : g.K;
-                    float v[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int k = k0 + kc * 4 + j;
-                        v[j] = (n < g.N && k < g.K) ? table_entry(tws, P, cplx, (int)n, k) : 0.0f;
-                    }
-                    rb[p][i] = __builtin_bit_cast(uint4, make_float4(v[0], v[1], v[2], v[3]));
-                } else {
+                if constexpr (!TABLE) {  // the table form assembles its B fragments in the slab loop
                     if (n < g.N && kb < KB) rb[p][i] = *reinterpret_cast<const uint4*>(Bp[p] + n * KB + kb);
                     else rb[p][i] = make_uint4(0u, 0u, 0u, 0u);
                 }
@@ -338,13 +339,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 }
             }
         }
+        if constexpr (!TABLE) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int i = 0; i < BCH; ++i) {
-                const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
-                *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = rb[p][i];
-            }
+                for (int i = 0; i < BCH; ++i) {
+                    const int c = tid + i * NT, row = c / CPR, kc = c % CPR;
+                    *reinterpret_cast<uint4*>(Bs + p * BN * RS + row * RS + kc * 16) = rb[p][i];
+                }
+        }
     };
 
     f32x16 acc[2][WN], acc2[2][WN];  // COMP: acc2 = the block accumulators
@@ -359,6 +362,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     load_tile(0);
     store_tile();
     __syncthreads();
+    // Table form: the B fragments of slab (t, s) come from the table alone, so
+    // those of the next slab are formed while this slab's products run.
+    uint4 bnext[WN];
+    auto table_frags = [&](int t, int s) {
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn)
+            bnext[bn] = __builtin_bit_cast(uint4, table_frag(tws, tP, tcplx, (int)n0 + wn * WC + bn * 32 + lr,
+                                                             t * BK + s * (SLAB / 4) + lh * 4, g.N, g.K));
+    };
+    if constexpr (TABLE) {
+        static_assert(NP == 1 && RD == 1 && FORM == FORM_FP32, "the table form is FP32");
+        table_frags(0, 0);
+    }
     for (int t = 0; t < nk; ++t) {
         if (t + 1 < nk) load_tile((t + 1) * BK);
 #pragma unroll
@@ -381,8 +397,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
                     for (int q = 0; q < RD; ++q) {
                         const int row = wn * WC + bn * 32 + lr;
-                        bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + off(q));
+                        if constexpr (TABLE) {
+                            bf[bn][p][q] = bnext[bn];  // formed during the previous slab
+                        } else {
+                            bf[bn][p][q] = *reinterpret_cast<const uint4*>(Bs + p * BN * RS + row * RS + off(q));
+                        }
                     }
+            if constexpr (TABLE) {  // the next slab's fragments (past the last: repeats in-range reads)
+                if (s + 1 < NSLAB) table_frags(t, s + 1);
+                else table_frags(t + 1 < nk ? t + 1 : t, 0);
+            }
             const int sa[2] = {0, 0}, sb[WN] = {};
             if constexpr (COMP) mfma_slab<FORM, NP, RD, WN>(af, bf, acc2, acc, sa, sb);
             else mfma_slab<FORM, NP, RD, WN>(af, bf, acc, acc2, sa, sb);
@@ -1159,14 +1183,19 @@ __global__ __launch_bounds__(NT) void dft_gemm_kernel(GemmArgs g) {
 }
 
 // FP32 with the DFT operand assembled from a P-entry twiddle table in LDS
-// (the table after the tile buffers, 8 P bytes, loaded once per block)
-// instead of read from the materialised N x K operand.
+// (the table after the A tile buffer, 8 P bytes, loaded once per block)
+// instead of read from the materialised N x K operand: every lane forms its
+// B fragments from the table, one slab ahead of the products that use them.
+constexpr size_t kTableTileBytes = (size_t)BM * RS;  // the table form stages only A tiles
+
 template <int WN>
 __global__ __launch_bounds__(NT) void dft_gemm_table_kernel(GemmArgs g, int P) {
     constexpr int BN = 64 * WN;
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
+    // The tile storage holds the A tile only (the table form never touches
+    // the B rows of GemmSmem); the table follows it.
     GemmSmem<FORM_FP32, WN>& sm = *reinterpret_cast<GemmSmem<FORM_FP32, WN>*>(dyn);
-    float2* tws = reinterpret_cast<float2*>(dyn + sizeof(GemmSmem<FORM_FP32, WN>));
+    float2* tws = reinterpret_cast<float2*>(dyn + kTableTileBytes);
     const float2* tw = reinterpret_cast<const float2*>(g.tw);
     for (int r = threadIdx.x; r < P; r += NT) tws[r] = tw[r];  // gemm_tile's first barrier publishes it
     const int64_t nm = (g.F + BM - 1) / BM, nn = (g.N + BN - 1) / BN;
@@ -1394,12 +1423,12 @@ hipError_t launch_dft_gemm(const GemmArgs& g, hipStream_t s) {
         if (g.form != FORM_FP32 || g.compensated) return hipErrorInvalidValue;
         constexpr int WN = 4, BN = 64 * WN;
         const int P = g.real_pack ? g.K : g.K / 2;
-        const size_t lds = sizeof(GemmSmem<FORM_FP32, WN>) + 8 * (size_t)P;
+        const size_t lds = kTableTileBytes + 8 * (size_t)P;
         static bool attr = false;
         if (!attr) {  // up to P = 8192 (64 KiB of table)
             hipError_t e = hipFuncSetAttribute((const void*)dft_gemm_table_kernel<WN>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(sizeof(GemmSmem<FORM_FP32, WN>) + 8 * 8192));
+                                               (int)(kTableTileBytes + 8 * 8192));
             if (e != hipSuccess) return e;
             attr = true;
         }
