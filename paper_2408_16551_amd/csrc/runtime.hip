@@ -172,7 +172,10 @@ tina_status tina_pfb_plan(const tina_pfb_desc* d, tina_pfb_plan_t* out) {
                 return bail(TINA_ERR_OUT_OF_MEMORY, "plan: scale workspace allocation");
         }
     }
-    e = hipDeviceSynchronize();
+    // The tables above were generated on the null stream: wait for it alone,
+    // so that a plan made while other work runs on non-blocking streams (a
+    // server's steps) does not wait for that work.
+    e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return bail(TINA_ERR_DEVICE, std::string("plan: ") + hipGetErrorString(e));
     *out = p;
     return TINA_OK;
