@@ -440,13 +440,16 @@ def batched_bench(torch, precisions=("fp32", "bf16x3", "fp32/factored"), steps=5
 _BATCHED_CAPACITY = {}
 
 
-def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5, dft="dense"):
+def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=30, dft="dense", warm=10):
     """Capacity C of the batched path on the serving mix: one request of
     log-uniform length 2^16-2^22 on each of the 64 logical streams, run as one
     tina_pfb_batch_execute (every item with its stream's plan and state),
     closed loop, inputs and outputs in HBM.  host=True: end to end from pinned
     host buffers (each pass copies every input in, runs the batch and copies
-    every output back, in order on one stream).  GSamples/s."""
+    every output back, in order on one stream).  GSamples/s, at steady
+    state: `warm` untimed passes first (the shader clock rises over the first
+    few milliseconds of load; 1 warm-up pass and 5 timed ones measured the FP8
+    mix at 42 GS/s, 10 and 30 at 47.5), then `reps` timed passes."""
     if (precision, host, dft) in _BATCHED_CAPACITY:
         return _BATCHED_CAPACITY[(precision, host, dft)]
     from paper_2408_16551_amd import workloads
@@ -481,7 +484,8 @@ def serving_mix_batched_capacity(torch, precision, host=False, seed=1005, reps=5
                 x.copy_(o, non_blocking=True)
 
     b = Batch(precision, max_items=len(items), workspace_bytes=2 << 30)
-    one_pass()
+    for _ in range(warm):
+        one_pass()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
@@ -537,13 +541,14 @@ def serving_check(torch, sv, pool, device, oracle_obj, seed, n_req=16):
 
 
 def serving_bench(torch, precision, budget_bytes, n_warm=200, n_meas=2000, rho=0.5, seed=1005, device=False,
-                  frames_per_step=1024, oracle_obj=None, max_active=64, use_graph=False, dft="dense"):
+                  frames_per_step=2048, oracle_obj=None, max_active=64, use_graph=False, dft="dense"):
     """Open-loop Poisson arrivals on 64 logical streams (channels from {512,
     1024, 4096}, 8-16 taps, complex64); each request is the next chunk of a
     random stream, length log-uniform 2^16-2^22.  The server runs up to
     max_active requests with samples to issue, frames_per_step frames each per
-    step (64 x 1024: at 0.8 of the capacity p99 was 1.6-1.9 ms against 3.5 ms
-    with 32 slots; 128 slots or 2048 frames measured no better).  Steps are
+    step (64 x 2048: FP8 at 0.8 of the steady-state capacity, p99 3.3 ms against
+    5.5 ms with 1024 frames; 4096 frames or 128 slots no better; at 0.5 the
+    same 0.85-0.9 ms).  Steps are
     plain launches: a graph replay leaves the device idle ~8 us longer per
     step and measured no lower latency.  The rate is rho times the
     batched path's capacity C on the same mix with the same buffer placement
