@@ -395,7 +395,7 @@ def sampled_check(oracle_obj, cases, seed, n_frames=64):
             "frames_per_stream": f"first M+1, last, {n_frames} random"}
 
 
-def batched_bench(torch, precisions=("fp32", "bf16x3", "fp32/factored"), steps=5, oracle_obj=None):
+def batched_bench(torch, precisions=("fp32", "bf16x3", "fp32/factored"), steps=20, oracle_obj=None, warm=10):
     """The ragged batch: 64 complex64 streams, log-uniform lengths 2^18-2^22,
     channels from {256, 512, 1024}, 16 taps, one persistent launch per stage,
     autotuned launch shapes ("fp32/factored": FP32 with the factored DFT,
@@ -415,7 +415,7 @@ def batched_bench(torch, precisions=("fp32", "bf16x3", "fp32/factored"), steps=5
         items = [(plans[s.P], x, o) for s, x, o in zip(specs, xd, outs)]
         b = Batch(prec, max_items=len(items), workspace_bytes=2 << 30)
         tf, tile_n = b.tune(items)
-        for _ in range(2):
+        for _ in range(warm):  # steady state: the shader clock rises over the first milliseconds of load
             b.execute(items)
         torch.cuda.synchronize()
         t = time.perf_counter()
