@@ -109,6 +109,8 @@ struct tina_pfb_batch_s {
     std::map<std::string, StepGraph> graphs;
     int64_t graph_gemm_grid = 0;  // GEMM grid the step graphs are captured with (0: no graphs)
     bool frame_stage = true;      // long per-frame scaled items run the single-pass frame stage
+    int64_t frame_stage_min = 2048;  // frames an item needs to run the frame stage
+    int frame_tf_target = 128;       // frames per frame-stage unit (rounded up to whole ring blocks of M)
     // Items whose plan takes the factored DFT (FP32): one launch per (P,
     // input type) over their frames, with the items' FftItem rows stored in
     // the table buffer after the items (fft_offset).
@@ -221,8 +223,6 @@ tina_status validate(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, std::vect
     return TINA_OK;
 }
 
-constexpr int64_t kFrameStageMinFrames = 2048;
-
 // Fills the host table for items [g.first, g.first + g.count) and returns the
 // launch parameters.  `dry` leaves state updates out (tuning runs).
 void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t>& frames, const GroupPlan& g,
@@ -307,16 +307,16 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         ga.Aqs = fa.qs;
         ga.fexp = fa.fexp;
         // Per-frame scaled items with frame rows of 1024 threads and at least
-        // kFrameStageMinFrames frames run in one pass (frame stage, units of
-        // fir_frame_batch_tf(M) frames); the others in the three FIR launches
+        // frame_stage_min frames run in one pass (frame stage, units of about
+        // frame_tf_target frames); the others in the three FIR launches
         // (units of 256 threads).  A frame-stage unit walks its frames one
         // ring block after another, so short items would take a unit's whole
-        // latency (~70 us measured in serving steps) for little work.
-        bi.fir_single = (b->frame_stage && form_scaled(b->form) && F >= kFrameStageMinFrames &&
+        // latency for little work.
+        bi.fir_single = (b->frame_stage && form_scaled(b->form) && F >= b->frame_stage_min &&
                          fir_frame_batch_vec(fa) != 0) ? 1 : 0;
         bi.frame_unit0 = r0;
         if (bi.fir_single) {
-            const int TF = fir_frame_batch_tf(p->M);
+            const int TF = p->M * ((b->frame_tf_target + p->M - 1) / p->M);
             bi.fir_tf = TF;
             fu[i] = 0;
             fc[i] = 1.0;
@@ -593,12 +593,17 @@ void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles) {
 }
 
 // Used by the server, which owns the batch and runs every step on its one
-// compute stream: steps keep every per-frame scaled item in the three FIR
-// launches (a step's items are short; a frame-stage unit's latency would set
-// the step's length), and no event orders a call after the previous one (a
-// recorded event leaves the device idle for ~5 us between two steps).
+// compute stream.  Per-frame scaled items of at least 256 frames take the
+// single-pass frame stage with short units (about 32 frames: a step's items
+// are short, and a 128-frame unit's latency, ~70 us, would set the step's
+// length; measured on the FP8 serving mix at 0.8 of the batched capacity, p99
+// 2.2-2.5 ms against 3.1-3.2 ms with the three launches, and the same at
+// 0.5).  No event orders a call after the previous one (a recorded event
+// leaves the device idle for ~5 us between two steps).
 void batch_set_server_mode(tina_pfb_batch_s* b) {
-    b->frame_stage = false;
+    b->frame_stage = true;
+    b->frame_stage_min = 256;
+    b->frame_tf_target = 32;
     b->one_stream = true;
 }
 

@@ -218,7 +218,6 @@ int fir_frame_batch_vec(const FirArgs& a) {
     return vec;
 }
 
-int fir_frame_batch_tf(int M) { return M * ((128 + M - 1) / M); }
 
 hipError_t launch_fir_frame_batch(const BatchTable* t, int qmode, int grid, hipStream_t s) {
     switch (qmode) {

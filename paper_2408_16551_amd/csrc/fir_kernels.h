@@ -56,8 +56,8 @@ int pick_vec(const FirArgs& a);
 int fir_frame_vec(const FirArgs& a);
 hipError_t launch_fir_frame(const FirArgs& a, hipStream_t s);
 // Batched form: the items flagged fir_single (fir_frame_batch_vec != 0),
-// frame runs of fir_frame_batch_tf(M) frames as units of the table's frame
-// stage.  grid: a multiple of 8 (one range per XCD).
+// runs of each item's fir_tf frames as units of the table's frame stage.
+// grid: a multiple of 8 (one range per XCD).
 hipError_t launch_fir_frame_batch(const BatchTable* t, int qmode, int grid, hipStream_t s);
 
 // Per-mode entry points (fir_out_*.hip).

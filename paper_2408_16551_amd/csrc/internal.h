@@ -202,9 +202,9 @@ constexpr int kGemmBM = 128, kGemmBN = 128;
 hipError_t launch_fir_batch(const BatchTable* t, int max_m, bool all_exact, int qmode, int grid, hipStream_t s,
                             bool frame_stage);
 // Per-frame scaled items a batch runs in one pass (whole frame rows of 1024
-// threads): the floats per thread, or 0 (three launches); frames per unit.
+// threads): the floats per thread, or 0 (three launches).  A unit walks the
+// item's fir_tf frames (a whole number of ring blocks of M).
 int fir_frame_batch_vec(const FirArgs& a);
-int fir_frame_batch_tf(int M);
 // FirArgs::qmode the FIR writes for a DFT form (0: FP32 y): every form but
 // FP32 takes its operand straight from the FIR.
 inline int form_fir_qmode(int form) {

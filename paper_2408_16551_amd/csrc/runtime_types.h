@@ -152,7 +152,7 @@ tina_status batch_run_items(tina_pfb_batch_s* b, tina_pfb_work* w, int32_t n, hi
 void batch_set_graph_bound(tina_pfb_batch_s* b, int64_t max_gemm_tiles);
 // Launches every step kernel variant once on an empty table (no graphs).
 tina_status batch_warm_kernels(tina_pfb_batch_s* b, hipStream_t s);
-// A batch owned by a server: one stream, no frame stage.
+// A batch owned by a server: one stream, short frame-stage units.
 void batch_set_server_mode(tina_pfb_batch_s* b);
 // Captures every step-graph variant in advance (needs the bound above).
 tina_status batch_prepare_graphs(tina_pfb_batch_s* b, hipStream_t s);

@@ -94,6 +94,31 @@ def test_server_streams_equal_one_shot_bitwise(precision, use_graph):
         assert r["t_submit_us"] <= r["t_admit_us"] <= r["t_done_us"]
 
 
+FRAME_STREAMS = [(512, 11, True), (1024, 16, True), (512, 8, True), (256, 16, False), (1024, 9, True)]
+
+
+@pytest.mark.parametrize("precision", ["fp8", "fp16x3"])
+def test_server_frame_stage_streams_equal_one_shot_bitwise(precision):
+    # 512 frames per step: pieces of 256 frames or more of the 512- and
+    # 1024-channel complex streams (frames of 1024 and 2048 floats) take the
+    # single-pass frame stage in short units, shorter pieces and the real
+    # stream the three FIR launches; every stream equals its one-shot pass.
+    g = np.random.Generator(np.random.PCG64(21))
+    reqs = []
+    for _ in range(16):
+        st = int(g.integers(len(FRAME_STREAMS)))
+        P = FRAME_STREAMS[st][0]
+        reqs.append((st, _rand(P * int(g.integers(200, 900)) + int(g.integers(P)), FRAME_STREAMS[st][2], g)))
+    got, results, stats = _serve(reqs, precision, use_graph=False, max_active=4, fps=512, streams=FRAME_STREAMS)
+    ref = _one_shot(reqs, precision, streams=FRAME_STREAMS)
+    for gg, r in zip(got, ref):
+        if r is None:
+            continue
+        assert gg.shape == r.shape
+        assert np.array_equal(gg, r)
+    assert stats["completed"] == len(reqs)
+
+
 FACTORED_STREAMS = [(256, 16, True), (512, 11, True), (256, 16, False), (1024, 9, True), (4096, 8, True)]
 
 
