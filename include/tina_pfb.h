@@ -288,7 +288,9 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t plan, const void* d_X, int64_t n
                                 void* stream);
 
 /* Per-stream filter state: (M-1)*P history samples plus fewer than P
- * residue samples, in device memory owned by the state.  Created zeroed. */
+ * residue samples, in device memory owned by the state.  Created zeroed.
+ * destroy, reset, export and import wait for all work on the device first:
+ * the state takes no stream, and calls that update it may have run on any. */
 tina_status tina_pfb_state_create(tina_pfb_plan_t plan, tina_pfb_state_t* out_state);
 tina_status tina_pfb_state_destroy(tina_pfb_state_t state);
 /* Zero the history and drop the residue (synchronous). */
