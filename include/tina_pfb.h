@@ -289,8 +289,13 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t plan, const void* d_X, int64_t n
 
 /* Per-stream filter state: (M-1)*P history samples plus fewer than P
  * residue samples, in device memory owned by the state.  Created zeroed.
- * destroy, reset, export and import wait for all work on the device first:
- * the state takes no stream, and calls that update it may have run on any. */
+ * The state takes no stream, and calls that update it may have run on any,
+ * so reset, export and import first wait for the work that last used it:
+ * when that was tina_pfb_execute or tina_pfb_synthesize of its plan outside
+ * stream capture, for that plan's latest call (a plan's calls run one after
+ * another across streams); after a batch, allocation-free or captured call,
+ * or before any call, for all work on the device.  destroy waits for all
+ * work on the device. */
 tina_status tina_pfb_state_create(tina_pfb_plan_t plan, tina_pfb_state_t* out_state);
 tina_status tina_pfb_state_destroy(tina_pfb_state_t state);
 /* Zero the history and drop the residue (synchronous). */

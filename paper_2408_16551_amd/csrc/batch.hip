@@ -259,6 +259,7 @@ void fill_table(tina_pfb_batch_s* b, tina_pfb_work* w, const std::vector<int64_t
         memset(&bi, 0, sizeof(bi));
         const int64_t F = frames[g.first + i];
         const int64_t r = st ? st->residue : 0;
+        if (st) st->plan_ordered = false;  // batch work is not covered by the plan's stream-order event
         FirArgs& fa = bi.fir;
         fa.prefix = st ? st->buf[st->cur] : nullptr;
         fa.plen = (int64_t)(p->M - 1) * p->W + r * p->cf;

@@ -257,6 +257,7 @@ tina_status execute_with(tina_pfb_plan_s* p, const void* d_in, int64_t n, void* 
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, name + ": hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
     if (w.use_plan) HIP_TRY(p->order.begin(s));
+    if (st) st->plan_ordered = false;  // until this call's work is covered by the order event
 
     FirArgs fa{};
     fa.prefix = st ? st->buf[st->cur] : nullptr;
@@ -375,6 +376,7 @@ tina_status execute_with(tina_pfb_plan_s* p, const void* d_in, int64_t n, void* 
         st->residue = r2;
     }
     if (w.use_plan) HIP_TRY(p->order.end(s));
+    if (st) st->plan_ordered = w.use_plan && p->order.valid;
     if (frames_written) *frames_written = F;
     return TINA_OK;
 }
@@ -500,6 +502,7 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t p, const void* d_X, int64_t F, v
     if (ds.err != hipSuccess) return fail(TINA_ERR_DEVICE, "synthesize: hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(p->order.begin(s));
+    if (st && F > 0) st->plan_ordered = false;  // until this call's work is covered by the order event
     const int64_t hist_floats = (int64_t)(p->M - 1) * p->W;
     const float* prefix = st ? st->buf[st->cur] : nullptr;
     int scratch = 0;
@@ -543,6 +546,7 @@ tina_status tina_pfb_synthesize(tina_pfb_plan_t p, const void* d_X, int64_t F, v
     }
     if (st && F > 0) st->cur ^= 1;
     HIP_TRY(p->order.end(s));
+    if (st && F > 0) st->plan_ordered = p->order.valid;
     if (written) *written = F * p->P;
     return TINA_OK;
 }
@@ -568,6 +572,17 @@ tina_status tina_pfb_state_create(tina_pfb_plan_t p, tina_pfb_state_t* out) {
     return TINA_OK;
 }
 
+// Waits until no enqueued work reads or writes the state's buffers.  Calls
+// of one plan are ordered across streams (each starts after the previous one
+// ends), so after an update by a plan call that the plan's stream-order event
+// covers, the plan's latest event is enough; otherwise (batch, allocation-free
+// or captured calls, or none yet) the whole device is waited for.
+static hipError_t wait_for_state(const tina_pfb_state_s* st) {
+    const tina_pfb_plan_s* p = st->plan;
+    if (st->plan_ordered && p->order.valid) return hipEventSynchronize(p->order.ev);
+    return hipDeviceSynchronize();
+}
+
 tina_status tina_pfb_state_destroy(tina_pfb_state_t st) {
     if (!st) return TINA_OK;
     DeviceScope ds(st->plan->device);
@@ -581,7 +596,7 @@ tina_status tina_pfb_state_destroy(tina_pfb_state_t st) {
 tina_status tina_pfb_state_reset(tina_pfb_state_t st) {
     if (!st) return fail(TINA_ERR_INVALID_ARGUMENT, "state_reset: NULL state");
     DeviceScope ds(st->plan->device);
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(wait_for_state(st));
     for (float* b : st->buf) HIP_TRY(hipMemset(b, 0, st->cap_floats * sizeof(float)));
     st->cur = 0;
     st->residue = 0;
@@ -602,7 +617,7 @@ tina_status tina_pfb_state_export(tina_pfb_state_t st, void* host, int64_t capac
     const int64_t n = (int64_t)(p->M - 1) * p->P + st->residue;
     if (capacity < n) return fail(TINA_ERR_INVALID_ARGUMENT, "state_export: host buffer too small");
     DeviceScope ds(p->device);
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(wait_for_state(st));
     if (n > 0) HIP_TRY(hipMemcpy(host, st->buf[st->cur], n * p->cf * sizeof(float), hipMemcpyDeviceToHost));
     if (n_samples) *n_samples = n;
     return TINA_OK;
@@ -614,7 +629,7 @@ tina_status tina_pfb_state_import(tina_pfb_state_t st, const void* host, int64_t
     const int64_t hist = (int64_t)(p->M - 1) * p->P;
     if (n < hist || n - hist >= p->P) return fail(TINA_ERR_INVALID_ARGUMENT, "state_import: sample count must be (M-1)*P + residue, residue < P");
     DeviceScope ds(p->device);
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(wait_for_state(st));
     if (n > 0) HIP_TRY(hipMemcpy(st->buf[0], host, n * p->cf * sizeof(float), hipMemcpyHostToDevice));
     st->cur = 0;
     st->residue = n - hist;

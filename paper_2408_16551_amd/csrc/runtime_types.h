@@ -140,6 +140,10 @@ struct tina_pfb_state_s {
     int cur = 0;
     int64_t residue = 0;     // samples
     int64_t cap_floats = 0;  // floats per buffer
+    // The last call that read or wrote buf was an execute or synthesize call
+    // of the plan that the plan's stream-order event covers (not a batch, an
+    // allocation-free or a captured call).
+    bool plan_ordered = false;
 };
 
 

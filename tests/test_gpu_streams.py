@@ -61,3 +61,42 @@ def test_device_request_waits_for_the_stream_writing_its_input():
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref)
     sv.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_state_calls_wait_for_the_plans_side_stream(cplx):
+    """Export right after an execute enqueued behind a held side stream, with
+    no synchronize: the state call waits for the plan's last call, so the
+    history it returns is the input's last (M-1)*P + residue samples.  Import
+    and the next execute then resume on another stream bit for bit."""
+    from paper_2408_16551_amd.pfb import Plan, State
+    P, M = 1024, 16
+    n = P * 3000 + 321
+    print(f"state on a side stream: P={P} M={M} complex={cplx}", flush=True)
+    xh = _x(2 * n, 21, cplx)
+    plan = Plan(P, M, "c64" if cplx else "r32", "hann", "fp32")
+    x1 = torch.from_numpy(xh[:n]).cuda()
+    x2 = torch.from_numpy(xh[n:]).cuda()
+    ref_state = State(plan)
+    plan(x1, state=ref_state)
+    ref_tail = plan(x2, state=ref_state).cpu()
+    torch.cuda.synchronize()
+    st = State(plan)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(20_000_000)      # hold the stream, so the call below ends late
+        plan(x1, state=st, stream=s)
+    hist = st.export()                      # no synchronize
+    want = xh[n - ((M - 1) * P + 321):n]
+    assert hist.shape == want.shape and np.array_equal(hist, want)
+    st2 = State(plan)
+    s2 = torch.cuda.Stream()
+    with torch.cuda.stream(s2):
+        torch.cuda._sleep(20_000_000)
+        plan(x1[: P * 10], state=st2, stream=s2)   # overwritten by the import below
+    st2.load_from(hist)                     # no synchronize: waits for s2's call first
+    with torch.cuda.stream(s2):
+        tail = plan(x2, state=st2, stream=s2)
+    s2.synchronize()
+    assert torch.equal(torch.view_as_real(tail.cpu()), torch.view_as_real(ref_tail))
+    plan.close()
