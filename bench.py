@@ -745,7 +745,7 @@ def main():
                     help="comma-separated workloads of the form tables: real (1024-channel real stream), "
                          "wide (4096-channel complex 60 dB stream)")
     ap.add_argument("--form-steps", type=int, default=0,
-                    help="timed steps per form (0: 20 on the real stream, 5 on the complex one)")
+                    help="timed steps per form (0: 20, after 5 warm-up steps, on both workloads)")
     ap.add_argument("--no-fir-only", action="store_true", help="skip the FIR-only run")
     ap.add_argument("--no-ops", action="store_true", help="skip the standalone building blocks")
     ap.add_argument("--copy-probe", action="store_true",
@@ -824,7 +824,7 @@ def main():
         del xd
         if "wide" in fw:
             wd = workloads.wide_dynamic_range()
-            result["forms"][wd.name] = forms_table(wd, forms, fs or 5, min(2, fs or 2), torch, o, 12)
+            result["forms"][wd.name] = forms_table(wd, forms, fs or 20, min(5, fs or 5), torch, o, 12)
             del wd
     if not args.no_forms and not args.no_fir_only:
         # FIR-only path on the real stream (the stage the FIR roofline measures).
